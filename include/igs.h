@@ -1,0 +1,206 @@
+/*
+ * igs.h -- C ABI of the MI355X (gfx950) iterated Gauss-Seidel GMRES solver.
+ *
+ * Solves A x = b, A real n x n (Section 1 of the paper), with restarted
+ * GMRES(m) whose Arnoldi-QR step needs ONE global reduction per iteration:
+ *
+ *   gs_iters = 2 : the one-reduce hybrid MGS-CGS step (Algorithm 4.2): the
+ *                  reduction [V, u]^T [u, A u], a lagged normalisation
+ *                  gamma^2 = u^T u - p^T p, the second Gauss-Seidel sweep
+ *                  t = (I + L)^{-1} V^T u lagged by one iteration, the first
+ *                  sweep of the next vector through Stephen's trick, and the
+ *                  Hessenberg column finished from eq:Aw.
+ *   gs_iters = 1 : the two-reduce step (Algorithm 4.1) stopped after its first
+ *                  Gauss-Seidel sweep (steps 4-13), which also needs a single
+ *                  reduction: [V, w]^T [w, A w].
+ *
+ * The least-squares problem (eq:llse) is reduced with Givens rotations on the
+ * device; x = x0 + V y closes each restart cycle.  Restarts begin from the
+ * explicit residual b - A x; the solve is converged when
+ * ||b - A x|| <= tol ||b|| at the start of a cycle, and a cycle ends early
+ * when its Arnoldi residual |g_J| <= tol ||b||.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Return value: IGS_OK (0), IGS_ENOCONV (1, x holds the last iterate), or a
+ *    negative error code.  No C++ exception crosses this boundary.
+ *    igs_last_error() gives a message for the last failing call on a context.
+ *  - "device pointer" means memory the caller allocated on the GPU the
+ *    context was created on (e.g. a torch tensor's data_ptr()); the library
+ *    never frees caller memory and keeps no reference to it after the call.
+ *  - All GPU work runs on the HIP stream passed to igs_create*; the calls are
+ *    synchronous: they return after that stream has finished the work.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - After IGS_EDEVICE the context must only be destroyed.
+ */
+#ifndef IGS_H
+#define IGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct igs_ctx igs_ctx;
+
+enum {
+  IGS_OK = 0,
+  IGS_ENOCONV = 1,    /* iteration budget used up; x holds the last iterate   */
+  IGS_EINVAL = -1,    /* invalid argument or input data (nothing was changed) */
+  IGS_ENOMEM = -2,    /* device or host allocation failed                      */
+  IGS_EDEVICE = -3,   /* a HIP runtime call failed                             */
+  IGS_ENOTIMPL = -4,  /* option combination not implemented                   */
+  IGS_ENUMERIC = -5   /* a non-finite value appeared during the solve          */
+};
+
+/* Why the last restart cycle ended (igs_info.last_cycle_status). */
+enum {
+  IGS_CYCLE_RUNNING = 0,
+  IGS_CYCLE_CONVERGED_AT_START = 1, /* ||r0|| <= tol ||b||: solve converged   */
+  IGS_CYCLE_ARNOLDI_CONVERGED = 2,  /* |g_J| <= tol ||b||                     */
+  IGS_CYCLE_FULL = 3,               /* m columns finished                     */
+  IGS_CYCLE_BREAKDOWN = 4,          /* gamma_j <= n eps ||H[0:j, j-1]||       */
+  IGS_CYCLE_LAGNORM = 5,            /* lagged norm cancelled; explicit norm   */
+  IGS_CYCLE_MAXIT = 6,              /* iteration budget reached               */
+  IGS_CYCLE_NONFINITE = 7           /* NaN or Inf in a reduction              */
+};
+
+/* Optional solver settings (igs_solve_opts).  Zero-initialise, then set. */
+typedef struct igs_opts {
+  int64_t maxit;        /* iteration budget; <= 0 means 20 n                    */
+  double lagnorm_tau;   /* gs_iters=2: if u^T u - p^T p < tau u^T u the norm is
+                           recomputed explicitly as ||u - V t|| (one extra
+                           reduction) and the cycle ends; <= 0 means 1e-4      */
+  int final_basis_vector; /* 1: also normalise v_J when a cycle ends, so the
+                             debug copy of V holds J+1 valid columns           */
+  int profile;          /* 1: time every launch of the step kernels with HIP
+                           events (igs_profile_get)                            */
+  int max_cycles;       /* > 0: stop after this many restart cycles            */
+  int keep_first_basis; /* 1: keep a device copy of the first cycle's V for
+                           igs_debug_copy_V (costs one copy of the basis)      */
+  int reserved[6];
+} igs_opts;
+
+/* Result summary of a solve.  Any pointer argument of this type may be NULL. */
+typedef struct igs_info {
+  int64_t iters;            /* Arnoldi iterations = sum of finished columns     */
+  int64_t cycles;           /* restart cycles run (incl. the final check)       */
+  double relres_true;       /* ||b - A x|| / ||b|| at the last explicit residual */
+  double arnoldi_relres;    /* |g_J| / ||b|| at the end of the last full cycle  */
+  double bnorm;             /* ||b||                                            */
+  int converged;            /* 1 when relres_true <= tol                        */
+  int breakdowns;           /* cycles ended by (happy) breakdown                */
+  int lagnorm_fallbacks;    /* explicit-norm recomputations (gs_iters=2)        */
+  int last_cycle_status;    /* IGS_CYCLE_* of the last cycle                     */
+  int first_cycle_J;        /* columns finished in the first cycle              */
+  int reserved;
+  double seconds;           /* wall time of the call                            */
+} igs_info;
+
+/*
+ * Create a solver context for a CSR operator (Section 1: a real n x n A).
+ *   row_ptr: int32[n+1], non-decreasing, row_ptr[0] = 0, row_ptr[n] = nnz.
+ *   col_idx: int32[nnz], each in [0, n).  vals: float64[nnz], finite.
+ *   ptrs_on_device: 0 = the three arrays are host memory, 1 = device memory.
+ *   hip_stream: hipStream_t for all work of this context (NULL: null stream).
+ * The arrays are validated and copied; the caller keeps ownership.
+ * Errors: IGS_EINVAL (n < 1, nnz < 0, malformed CSR, non-finite values),
+ *         IGS_ENOMEM, IGS_EDEVICE.  On error *out is set to NULL.
+ */
+int igs_create(igs_ctx **out, int64_t n, int64_t nnz, const int32_t *row_ptr,
+               const int32_t *col_idx, const double *vals, int ptrs_on_device,
+               void *hip_stream);
+
+/*
+ * Create a solver context for a dense operator.
+ *   A: float64, row-major, n rows of leading dimension lda >= n, finite.
+ *   ptr_on_device: 0 = host memory, 1 = device memory.
+ * The matrix is copied into device memory the context owns.
+ * Errors as igs_create.
+ */
+int igs_create_dense(igs_ctx **out, int64_t n, const double *A, int64_t lda,
+                     int ptr_on_device, void *hip_stream);
+
+/*
+ * Solve A x = b.
+ *   b: device pointer, float64[n], 16-byte aligned.
+ *   x: device pointer, float64[n], 16-byte aligned; in: x0, out: the solution.
+ *   restart: m >= 1 (clamped to n and to IGS_MAX_RESTART).
+ *   tol: relative residual tolerance >= 0.
+ *   gs_iters: 1 or 2 (see the top of this file).
+ *   info: optional result summary.
+ * Workspace (the n x (m+1) basis and the small matrices) is allocated on the
+ * first call and reused while restart does not grow.
+ * Returns IGS_OK when converged, IGS_ENOCONV when the budget ran out (x holds
+ * the last iterate), IGS_EINVAL (bad argument, non-finite b or x0; x is
+ * unchanged), IGS_ENUMERIC, IGS_ENOMEM or IGS_EDEVICE.
+ */
+int igs_solve(igs_ctx *ctx, const double *b, double *x, int restart, double tol,
+              int gs_iters, igs_info *info);
+
+/* igs_solve with optional settings (opts may be NULL = defaults). */
+int igs_solve_opts(igs_ctx *ctx, const double *b, double *x, int restart, double tol,
+                   int gs_iters, const igs_opts *opts, igs_info *info);
+
+/* Release the context and everything it allocated.  NULL is accepted. */
+int igs_destroy(igs_ctx *ctx);
+
+/* Message of the last failing call on ctx ("" if none); valid until the next
+ * call on ctx.  With ctx == NULL: the last failure of igs_create*. */
+const char *igs_last_error(const igs_ctx *ctx);
+
+/* Largest supported restart length. */
+#define IGS_MAX_RESTART 512
+
+/* ---- Inspection of the FIRST restart cycle of the last solve (tests) ----- */
+
+/* Copy the Hessenberg matrix H (before Givens rotation) of the first cycle to
+ * host memory, column-major with leading dimension ldh >= J+1; *ncols = J.
+ * H_host must hold ldh * J doubles. */
+int igs_debug_copy_H(igs_ctx *ctx, double *H_host, int ldh, int *ncols);
+
+/* Copy the basis V of the first cycle (J+1 columns, of which column J is
+ * valid only with final_basis_vector) to a device buffer, column-major with
+ * leading dimension ldv >= n; *ncols = J + 1.  V_dev must hold ldv*(J+1).
+ * Needs opts.keep_first_basis = 1 in the last solve, else IGS_EINVAL. */
+int igs_debug_copy_V(igs_ctx *ctx, double *V_dev, int64_t ldv, int *ncols);
+
+/* ---- Step kernels on caller buffers (unit tests of each hot-path step) --- */
+
+/* z = A u with the context's operator kernel.  u, z: device float64[n]. */
+int igs_kernel_spmv(igs_ctx *ctx, const double *u, double *z);
+
+/* The fused reduction of one iteration: with u = V[:, j],
+ *   P[c] = V[:, c]^T u and Q[c] = V[:, c]^T z for c = 0..j.
+ * V: device, column-major, ldv >= n, j+1 columns; z: device float64[n] or
+ * NULL (then Q is not formed).  P_host, Q_host: host float64[j+1] (Q_host may
+ * be NULL).  0 <= j < IGS_MAX_RESTART. */
+int igs_kernel_reduce(igs_ctx *ctx, const double *V, int64_t ldv, int j,
+                      const double *z, double *P_host, double *Q_host);
+
+/* The basis update of one iteration, in place on V:
+ *   v = (V[:, j] - V[:, 0:j] t) * inv_gamma            -> V[:, j]
+ *   u = z * inv_gamma - V[:, 0:j] r1[0:j] - v r1[j]    -> V[:, j+1]
+ * V: device, column-major, ldv >= n, j+2 columns; z: device float64[n];
+ * t_host: host float64[j] (NULL = zeros); r1_host: host float64[j+1]. */
+int igs_kernel_update(igs_ctx *ctx, double *V, int64_t ldv, int j, const double *z,
+                      const double *t_host, const double *r1_host, double inv_gamma);
+
+/* ---- Per-kernel timing (opts.profile = 1) --------------------------------- */
+
+enum { IGS_K_SPMV = 0, IGS_K_REDUCE = 1, IGS_K_UPDATE = 2, IGS_K_XUPDATE = 3,
+       IGS_K_RESIDUAL = 4, IGS_K_COUNT = 5 };
+
+/* Totals over the timed launches of kernel `which` since the last reset:
+ * launches, summed HIP-event milliseconds, and summed algorithmic bytes
+ * (the minimum HBM traffic of each launch, computed from its shape). */
+int igs_profile_get(igs_ctx *ctx, int which, int64_t *launches, double *total_ms,
+                    double *total_bytes);
+int igs_profile_reset(igs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGS_H */

@@ -247,6 +247,17 @@ def stephen_trick(q_scaled: np.ndarray, beta_scaled: float, t: np.ndarray, gamma
     return np.concatenate([q_scaled, [last]])
 
 
+def normalise_after_second_sweep(Vt_old: np.ndarray, u: np.ndarray, t: np.ndarray,
+                                 gamma: float) -> np.ndarray:
+    """v_j = (u_j - V_{0:j} t) / gamma (steps 10-11 of Algorithm 4.2)."""
+    return (u - Vt_old.T @ t) / gamma
+
+
+def first_sweep_next(Vt_new: np.ndarray, z: np.ndarray, gamma: float, r1: np.ndarray) -> np.ndarray:
+    """u_{j+1} = A u_j / gamma - V_{0:j+1} r1 (step 13 of Algorithm 4.2)."""
+    return z / gamma - Vt_new.T @ r1
+
+
 def lagged_norm_sq(alpha: float, p: np.ndarray) -> float:
     """||u - V V^T u||^2 by Pythagoras: u^T u - p^T p (step 6 of Algorithm 4.2)."""
     return alpha - float(p @ p)
@@ -351,7 +362,7 @@ def cycle_igs_1r(op, r0: np.ndarray, m: int, stop: StopRule, jacobi: bool = Fals
             if _breakdown(gamma, H[:j, j - 1], n):
                 return _pack(Vt, H, L, j, gls, rho, res, "breakdown", gammas, fallbacks)
         L[j, :j] = p / gamma                                # step 9
-        Vt[j] = (u - Vt[:j].T @ t) / gamma                  # steps 10-11
+        Vt[j] = normalise_after_second_sweep(Vt[:j], u, t, gamma)   # steps 10-11
         if j > 0 and res[-1] <= stop.tol_abs:
             return _pack(Vt, H, L, j, gls, rho, res, "converged", gammas, fallbacks)
         if fallback:
@@ -363,6 +374,6 @@ def cycle_igs_1r(op, r0: np.ndarray, m: int, stop: StopRule, jacobi: bool = Fals
         qs = q / gamma                                      # step 7
         bs = beta / gamma / gamma                           # steps 7-8
         r1 = stephen_trick(qs, bs, t, gamma)                # step 12
-        Vt[j + 1] = z / gamma - Vt[: j + 1].T @ r1          # step 13
+        Vt[j + 1] = first_sweep_next(Vt[: j + 1], z, gamma, r1)     # step 13
         r1_prev, t_prev, gamma_prev = r1, t, gamma
     raise AssertionError("unreachable")

@@ -1,0 +1,114 @@
+// Internal types shared by the device kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace igs {
+
+constexpr int kWave = 64;
+constexpr int kReduceThreads = 512;     // 8 waves per block in the fused reduction
+constexpr int kReduceWaves = kReduceThreads / kWave;
+constexpr int kUpdateThreads = 256;
+constexpr int kUpdateRows = 4;          // rows per thread in the update / x-update passes
+constexpr int kGroup = 32;              // blocks per first-level group of a grid reduction
+constexpr int kMaxBlocks = 2048;
+constexpr int kMaxGroups = kMaxBlocks / kGroup;
+
+// How a restart cycle ended (mirrors IGS_CYCLE_* in igs.h).
+enum CycleStatus : int {
+  kRunning = 0, kConvStart = 1, kConverged = 2, kFull = 3,
+  kBreakdown = 4, kLagnorm = 5, kMaxit = 6, kNonfinite = 7
+};
+
+// What the update kernel of an iteration does.
+enum UpdateMode : int {
+  kUpdNone = 0,      // nothing (cycle ended without needing v_j)
+  kUpdNormal = 1,    // v_j and u_{j+1}
+  kUpdVOnly = 2,     // v_j only (last vector of a cycle, on request)
+  kUpdFallback = 3   // lagged norm cancelled: w = u - V t, explicit ||w||, finish column
+};
+
+// Control block in device memory.  Written by the last block of the fused
+// reduction (and by the fallback update); read at the start of every step
+// kernel so that kernels queued after the end of a cycle do nothing.
+struct Ctl {
+  int active;          // 1 while the current cycle runs
+  int J;               // finished Hessenberg columns in the current cycle
+  int status;          // CycleStatus
+  int mode;            // UpdateMode for iteration mode_iter
+  int mode_iter;       // iteration the mode applies to (-1: none)
+  int breakdowns;
+  int fallbacks;
+  int gs;              // 1 or 2 Gauss-Seidel sweeps
+  int final_v;
+  int m;               // restart length of the cycle
+  long long n;
+  long long its_before;  // iterations finished before this cycle
+  long long maxit;
+  double bnorm;        // ||b||
+  double tol;          // relative tolerance
+  double tol_abs;      // tol * ||b||
+  double lagnorm_tau;
+  double rho;          // ||r0|| of the cycle
+  double gabs;         // |g_J| after the last finished column
+  double inv_gamma;    // 1 / gamma_j for the update kernel
+  double gamma_prev;   // gamma of the previous iteration
+  int nonfinite_in;    // count of non-finite entries in b and x0
+  int pad;
+};
+
+// Device operator: CSR or dense row-major.
+struct Op {
+  int dense;
+  long long n;
+  const int* row_ptr;
+  const int* col_idx;
+  const double* vals;
+  const double* A;     // dense
+  long long lda;
+  int lpr;             // CSR lanes per row
+};
+
+// Device workspace of a context (all device pointers).
+struct Work {
+  double* V; long long ldv;      // basis, column-major, m+1 columns
+  double* z;                     // A u of the current iteration
+  double* H; double* R;          // Hessenberg (unrotated / rotated), column-major, ld = ldh
+  double* T;                     // (I + L)^{-1}, row-major, ld = ldt
+  double* L;                     // strictly lower L, column-major, ld = ldt
+  int ldh; int ldt;
+  double* cs; double* sn; double* g; double* y;
+  double* coef_t;                // t of the current iteration (prev at the next)
+  double* coef_r1;               // r1 of the current iteration (prev at the next)
+  double* part;                  // per-block partial sums [kMaxBlocks][pstride]
+  double* gpart;                 // per-group partial sums [kMaxGroups][pstride]
+  int pstride;
+  unsigned* tickets;             // [kMaxGroups + 1] arrival counters
+  Ctl* ctl;
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+
+hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, hipStream_t s);
+hipError_t launch_residual(const Op& op, const double* b, const double* x, double* r,
+                           const Work& w, long long its_before, long long maxit, int m,
+                           int gs, int final_v, double tol, double tau, hipStream_t s);
+hipError_t launch_bnorm(const double* b, const double* x, long long n, const Work& w,
+                        hipStream_t s);
+hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,
+                         int* nblocks_out);
+hipError_t launch_update(const Work& w, long long n, int j, int gs, hipStream_t s);
+hipError_t launch_lsq(const Work& w, int m, hipStream_t s);
+hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s);
+
+// Step kernels on caller buffers (no control block).
+hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j, const double* z,
+                             double* part, double* gpart, int pstride, unsigned* tickets,
+                             double* out, hipStream_t s);
+hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
+                             const double* t, const double* r1, double inv_gamma, hipStream_t s);
+
+int reduce_grid(long long n);
+
+}  // namespace igs

@@ -1,0 +1,955 @@
+// gfx950 kernels of the one-reduction Arnoldi step of iterated Gauss-Seidel GMRES.
+//
+// Per Arnoldi iteration j (0-based; iteration j normalises basis vector j and
+// finishes Hessenberg column j-1) the host queues three kernels:
+//
+//   spmv     z = A u_j                              (operator apply; skipped at j = m)
+//   reduce   [V_{0:j}, u_j]^T [u_j, z]              (the ONE global reduction)
+//            + in the last block to arrive: the small solve (lagged norm,
+//              second Gauss-Seidel sweep, Stephen's trick, Hessenberg column,
+//              Givens rotation, stopping tests)
+//   update   v_j = (u_j - V t) / gamma,
+//            u_{j+1} = z / gamma - V r1 - v_j r1_j     (one pass over V)
+//
+// u_j lives in column j of V until the update overwrites it with v_j.  All
+// reductions are deterministic: every partial sum is formed in a fixed order
+// that depends only on the launch shape.
+#include "igs_internal.h"
+
+#include <math.h>
+
+namespace igs {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int load_agent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool ctl_active(const Ctl* c) { return load_agent(&c->active) != 0; }
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous range of logical blocks so that the neighbour gathers of the
+// operator apply hit the L2 of that XCD.
+__device__ __forceinline__ long long xcd_block(int b, int nb) {
+  if (nb % 8 != 0) return b;
+  return (long long)(b % 8) * (nb / 8) + b / 8;
+}
+
+// Deterministic grid-wide sum of nv per-block values.
+// Every block calls this after writing part[blockIdx.x * pstride + v], v < nv.
+// Blocks are combined in groups of kGroup (the last block of a group sums its
+// group), then the last group sums the group totals.  Returns true in exactly
+// one block, in which out[v] (shared memory) then holds the total.
+__device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
+                                 int nv, double* out) {
+  __shared__ int s_last;
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int ngroups = (nb + kGroup - 1) / kGroup;
+  const int g = b / kGroup;
+  const int gsize = min(kGroup, nb - g * kGroup);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(&tickets[g], 1u);
+    s_last = (prev == (unsigned)(gsize - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    double acc = 0.0;
+    const double* p = part + (size_t)g * kGroup * pstride + v;
+    for (int k = 0; k < gsize; ++k) acc += p[(size_t)k * pstride];
+    gpart[(size_t)g * pstride + v] = acc;
+  }
+  if (threadIdx.x == 0) tickets[g] = 0u;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(&tickets[kMaxGroups], 1u);
+    s_last = (prev == (unsigned)(ngroups - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < ngroups; ++k) acc += gpart[(size_t)k * pstride + v];
+    out[v] = acc;
+  }
+  if (threadIdx.x == 0) tickets[kMaxGroups] = 0u;
+  __syncthreads();
+  return true;
+}
+
+// Dot product of two shared-memory vectors by one wave (lanes stride by 64);
+// the result is returned in every lane of wave 0.
+__device__ __forceinline__ double wave_dot(const double* a, const double* b, int len) {
+  const int lane = threadIdx.x % kWave;
+  double acc = 0.0;
+  for (int i = lane; i < len; i += kWave) acc = fma(a[i], b[i], acc);
+  return wave_sum(acc);
+}
+
+// ---------------------------------------------------------------------------
+// operator apply: z = A u  (or r = b - A x)
+// ---------------------------------------------------------------------------
+
+// CSR with LPR lanes per row: the lanes of a row read its entries as one
+// contiguous, coalesced segment and combine them with a butterfly.
+template <int LPR>
+__global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci,
+                                                       const double* __restrict__ va,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y,
+                                                       const double* __restrict__ bsub,
+                                                       const Ctl* __restrict__ gate) {
+  if (gate != nullptr && !ctl_active(gate)) return;
+  const long long lb = xcd_block(blockIdx.x, gridDim.x);
+  const long long row = (lb * blockDim.x + threadIdx.x) / LPR;
+  const int lane = threadIdx.x % LPR;
+  if (row >= n) return;  // the LPR lanes of a row leave together
+  const int s = rp[row];
+  const int e = rp[row + 1];
+  double acc = 0.0;
+  for (int k = s + lane; k < e; k += LPR) acc = fma(va[k], x[ci[k]], acc);
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+  if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
+}
+
+// Dense row-major operator: one wave per row, 16-byte loads.
+__global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const double* __restrict__ A,
+                                                         long long lda,
+                                                         const double* __restrict__ x,
+                                                         double* __restrict__ y,
+                                                         const double* __restrict__ bsub,
+                                                         const Ctl* __restrict__ gate) {
+  if (gate != nullptr && !ctl_active(gate)) return;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const long long row = (long long)blockIdx.x * (blockDim.x / kWave) + wave;
+  if (row >= n) return;
+  const double* a = A + row * lda;
+  double acc0 = 0.0, acc1 = 0.0;
+  const long long n2 = n & ~1LL;
+  for (long long c = 2 * lane; c < n2; c += 2 * kWave) {
+    const double2 av = *reinterpret_cast<const double2*>(a + c);
+    const double2 xv = *reinterpret_cast<const double2*>(x + c);
+    acc0 = fma(av.x, xv.x, acc0);
+    acc1 = fma(av.y, xv.y, acc1);
+  }
+  if ((n & 1) && lane == 0) acc0 = fma(a[n - 1], x[n - 1], acc0);
+  const double acc = wave_sum(acc0 + acc1);
+  if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
+}
+
+static hipError_t op_apply(const Op& op, const double* x, double* y, const double* bsub,
+                           const Ctl* gate, hipStream_t s) {
+  if (op.dense) {
+    const int rows_per_block = 4;
+    const unsigned grid = (unsigned)((op.n + rows_per_block - 1) / rows_per_block);
+    hipLaunchKernelGGL(gemv_dense_kernel, dim3(grid), dim3(256), 0, s, op.n, op.A, op.lda, x, y,
+                       bsub, gate);
+    return hipGetLastError();
+  }
+  const long long threads = op.n * op.lpr;
+  unsigned grid = (unsigned)((threads + 255) / 256);
+  if (grid >= 64) grid = (grid + 7) / 8 * 8;  // multiple of 8 for the XCD mapping
+  switch (op.lpr) {
+#define IGS_SPMV_CASE(L)                                                                        \
+  case L:                                                                                       \
+    hipLaunchKernelGGL(spmv_csr_kernel<L>, dim3(grid), dim3(256), 0, s, op.n, op.row_ptr,       \
+                       op.col_idx, op.vals, x, y, bsub, gate);                                  \
+    break;
+    IGS_SPMV_CASE(1) IGS_SPMV_CASE(2) IGS_SPMV_CASE(4) IGS_SPMV_CASE(8) IGS_SPMV_CASE(16)
+    IGS_SPMV_CASE(32) IGS_SPMV_CASE(64)
+#undef IGS_SPMV_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, hipStream_t s) {
+  return op_apply(op, u, z, nullptr, gate, s);
+}
+
+// ---------------------------------------------------------------------------
+// cycle start: reset the control block, then r0 = b - A x into V[:, 0]
+// ---------------------------------------------------------------------------
+
+__global__ void cycle_begin_kernel(Ctl* c, long long its_before, long long maxit, int m, int gs,
+                                   int final_v, double tol, double tau) {
+  if (threadIdx.x != 0) return;
+  c->active = 1;
+  c->J = 0;
+  c->status = kRunning;
+  c->mode = kUpdNone;
+  c->mode_iter = -1;
+  c->its_before = its_before;
+  c->maxit = maxit;
+  c->m = m;
+  c->gs = gs;
+  c->final_v = final_v;
+  c->tol = tol;
+  c->tol_abs = tol * c->bnorm;
+  c->lagnorm_tau = tau;
+  c->gabs = 0.0;
+}
+
+hipError_t launch_residual(const Op& op, const double* b, const double* x, double* r,
+                           const Work& w, long long its_before, long long maxit, int m, int gs,
+                           int final_v, double tol, double tau, hipStream_t s) {
+  hipLaunchKernelGGL(cycle_begin_kernel, dim3(1), dim3(64), 0, s, w.ctl, its_before, maxit, m, gs,
+                     final_v, tol, tau);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return op_apply(op, x, r, b, nullptr, s);
+}
+
+// ---------------------------------------------------------------------------
+// ||b|| and a finiteness check of b and x0 (once per solve)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void bnorm_kernel(const double* __restrict__ b,
+                                                    const double* __restrict__ x, long long n,
+                                                    Work w) {
+  __shared__ double red[2][256 / kWave];
+  __shared__ double tot[2];
+  double s2 = 0.0, bad = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double bi = b[i];
+    const double xi = x[i];
+    s2 = fma(bi, bi, s2);
+    bad += (isfinite(bi) ? 0.0 : 1.0) + (isfinite(xi) ? 0.0 : 1.0);
+  }
+  s2 = wave_sum(s2);
+  bad = wave_sum(bad);
+  const int wave = threadIdx.x / kWave;
+  if (threadIdx.x % kWave == 0) {
+    red[0][wave] = s2;
+    red[1][wave] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double acc = 0.0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) acc += red[threadIdx.x][k];
+    w.part[(size_t)blockIdx.x * w.pstride + threadIdx.x] = acc;
+  }
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2, tot)) return;
+  if (threadIdx.x == 0) {
+    w.ctl->bnorm = sqrt(tot[0]);
+    w.ctl->nonfinite_in = (int)tot[1];
+    w.ctl->breakdowns = 0;
+    w.ctl->fallbacks = 0;
+  }
+}
+
+hipError_t launch_bnorm(const double* b, const double* x, long long n, const Work& w,
+                        hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(bnorm_kernel, dim3((unsigned)blocks), dim3(256), 0, s, b, x, n, w);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Givens rotation of a finished Hessenberg column (eq:llse), one thread.
+// col[0..c+1] (shared) holds column c before rotation; on return R[:, c],
+// cs[c], sn[c] and g[c], g[c+1] are updated and |g[c+1]| is returned.
+// ---------------------------------------------------------------------------
+
+__device__ double givens_column(const Work& w, int c, double* col, const double* scs,
+                                const double* ssn) {
+  for (int i = 0; i < c; ++i) {
+    const double a = col[i];
+    const double b = col[i + 1];
+    col[i] = scs[i] * a + ssn[i] * b;
+    col[i + 1] = -ssn[i] * a + scs[i] * b;
+  }
+  const double a = col[c];
+  const double b = col[c + 1];
+  const double d = hypot(a, b);
+  double cs = 1.0, sn = 0.0;
+  if (d != 0.0) {
+    cs = a / d;
+    sn = b / d;
+  }
+  col[c] = d;
+  col[c + 1] = 0.0;
+  w.cs[c] = cs;
+  w.sn[c] = sn;
+  const double gc = w.g[c];
+  w.g[c + 1] = -sn * gc;
+  w.g[c] = cs * gc;
+  return fabs(sn * gc);
+}
+
+// Finish Hessenberg column j-1 with subdiagonal gamma: store H and the rotated
+// column, apply the rotation, and run the breakdown test.  hcol (shared) holds
+// H[0:j, j-1]; scratch needs 2*j doubles.  Called by all threads of a block.
+// Returns 1 on breakdown, 0 otherwise; ctl->gabs is updated.
+__device__ int finish_column(const Work& w, int j, double* hcol, double gamma, double* scratch,
+                             long long n) {
+  __shared__ double s_hn;
+  __shared__ int s_brk;
+  double* scs = scratch;
+  double* ssn = scratch + j;
+  const int c = j - 1;
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    w.H[(size_t)c * w.ldh + i] = hcol[i];
+    if (i < c) {
+      scs[i] = w.cs[i];
+      ssn[i] = w.sn[i];
+    }
+  }
+  if (threadIdx.x == 0) w.H[(size_t)c * w.ldh + j] = gamma;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const double hn2 = wave_dot(hcol, hcol, j);
+    if (threadIdx.x == 0) s_hn = sqrt(hn2);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    hcol[j] = gamma;
+    const double gabs = givens_column(w, c, hcol, scs, ssn);
+    w.ctl->gabs = gabs;
+    const double eps = 2.220446049250313e-16;
+    s_brk = (gamma <= (double)n * eps * s_hn) ? 1 : 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) w.R[(size_t)c * w.ldh + i] = hcol[i];
+  const int brk = s_brk;
+  __syncthreads();
+  return brk;
+}
+
+// ---------------------------------------------------------------------------
+// The small solve of iteration j, run by the last block of the reduction.
+// P[c] = V_c^T u, Q[c] = V_c^T z for c <= j (P[j] = u^T u, Q[j] = u^T z).
+// ---------------------------------------------------------------------------
+
+__device__ void small_solve(const Work& w, long long n, int j, bool tail, const double* P,
+                            const double* Q, double* sm) {
+  Ctl* ctl = w.ctl;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int nw = blockDim.x / kWave;
+  const int ldt = w.ldt;
+  // shared scratch, each of length j + 2
+  const int L1 = j + 2;
+  double* st = sm;            // t (second sweep coefficients)
+  double* shc = sm + L1;      // finished column j-1
+  double* sr1 = sm + 2 * L1;  // new first-sweep coefficients
+  double* sx = sm + 3 * L1;   // temp
+  double* sl = sm + 4 * L1;   // new row of L
+  double* sgiv = sm + 5 * L1; // 2 * L1 for the rotations
+  __shared__ double s_gamma, s_pp;
+  __shared__ int s_flag;
+
+  const int gs = ctl->gs;
+  const int m = ctl->m;
+  const double alpha = P[j];
+  const double beta = tail ? 0.0 : Q[j];
+
+  if (!isfinite(alpha) || !isfinite(beta)) {
+    if (tid == 0) {
+      ctl->status = kNonfinite;
+      ctl->J = j > 0 ? j - 1 : 0;
+      ctl->active = 0;
+    }
+    return;
+  }
+
+  if (j == 0) {
+    if (tid == 0) {
+      const double gamma = sqrt(alpha);
+      ctl->rho = gamma;
+      ctl->gabs = gamma;
+      w.g[0] = gamma;
+      if (gamma <= ctl->tol_abs) {
+        ctl->status = kConvStart;
+        ctl->J = 0;
+        ctl->active = 0;
+      } else {
+        w.T[0] = 1.0;
+        const double ig = 1.0 / gamma;
+        w.coef_r1[0] = beta * ig * ig;
+        ctl->inv_gamma = ig;
+        ctl->gamma_prev = gamma;
+        ctl->mode = kUpdNormal;
+        ctl->mode_iter = 0;
+      }
+    }
+    return;
+  }
+
+  // ---- second sweep t = (I + L_{0:j,0:j})^{-1} p = T_j p  (gs = 2) ----------
+  if (gs == 2) {
+    for (int i = wave; i < j; i += nw) {
+      const double* trow = w.T + (size_t)i * ldt;
+      double acc = 0.0;
+      for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], P[c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) st[i] = acc;
+    }
+  } else {
+    for (int i = tid; i < j; i += blockDim.x) st[i] = 0.0;
+  }
+  if (wave == 0) {
+    const double pp = wave_dot(P, P, j);
+    if (lane == 0) s_pp = pp;
+  }
+  __syncthreads();
+
+  // ---- finished column j-1:  r1_prev + t - H[0:j, 0:j-1] (t_prev / gamma_prev)
+  {
+    const double igp = 1.0 / ctl->gamma_prev;
+    for (int i = tid; i < j - 1; i += blockDim.x) sx[i] = w.coef_t[i] * igp;
+    __syncthreads();
+    for (int i = tid; i < j; i += blockDim.x) {
+      double acc = 0.0;
+      if (gs == 2) {
+        for (int c = (i > 0 ? i - 1 : 0); c < j - 1; ++c)
+          acc = fma(w.H[(size_t)c * w.ldh + i], sx[c], acc);
+      }
+      shc[i] = w.coef_r1[i] + st[i] - acc;
+    }
+  }
+  __syncthreads();
+
+  // ---- lagged norm (gs = 2) or explicit norm (gs = 1) ------------------------
+  if (tid == 0) {
+    int fb = 0;
+    double gamma;
+    if (gs == 2) {
+      const double g2 = alpha - s_pp;
+      if (!(g2 >= ctl->lagnorm_tau * alpha) || !(g2 > 0.0)) fb = 1;
+      gamma = fb ? 0.0 : sqrt(g2);
+    } else {
+      gamma = sqrt(alpha);
+    }
+    s_gamma = gamma;
+    s_flag = fb;
+  }
+  __syncthreads();
+  if (s_flag) {
+    // Cancellation in u^T u - p^T p: store the column without its subdiagonal
+    // and let the update kernel form w = u - V t and its explicit norm.
+    for (int i = tid; i < j; i += blockDim.x) {
+      w.H[(size_t)(j - 1) * w.ldh + i] = shc[i];
+      w.coef_t[i] = st[i];
+    }
+    if (tid == 0) {
+      ctl->mode = kUpdFallback;
+      ctl->mode_iter = j;
+    }
+    return;
+  }
+  const double gamma = s_gamma;
+  const double ig = 1.0 / gamma;
+
+  // ---- Hessenberg column, Givens rotation, breakdown test --------------------
+  const int brk = finish_column(w, j, shc, gamma, sgiv, n);
+  if (brk) {
+    if (tid == 0) {
+      ctl->status = kBreakdown;
+      ctl->J = j;
+      ctl->active = 0;
+      ctl->breakdowns += 1;
+    }
+    return;
+  }
+
+  // ---- new row of L (p / gamma) and of T = (I + L)^{-1} (eq:block) ---------
+  for (int c = tid; c < j; c += blockDim.x) {
+    const double l = P[c] * ig;
+    sl[c] = l;
+    w.L[(size_t)c * ldt + j] = l;
+  }
+  __syncthreads();
+  for (int c = tid; c < j; c += blockDim.x) {
+    double acc = 0.0;
+    for (int i = c; i < j; ++i) acc = fma(sl[i], w.T[(size_t)i * ldt + c], acc);
+    w.T[(size_t)j * ldt + c] = -acc;
+  }
+  if (tid == 0) w.T[(size_t)j * ldt + j] = 1.0;
+
+  // ---- stopping tests ----------------------------------------------------------
+  if (tid == 0) {
+    int st_code = kRunning;
+    if (ctl->gabs <= ctl->tol_abs) st_code = kConverged;
+    else if (j >= m) st_code = kFull;
+    else if (ctl->its_before + j >= ctl->maxit) st_code = kMaxit;
+    s_flag = st_code;
+  }
+  __syncthreads();
+  if (s_flag != kRunning) {
+    for (int i = tid; i < j; i += blockDim.x) w.coef_t[i] = st[i];
+    if (tid == 0) {
+      ctl->status = s_flag;
+      ctl->J = j;
+      ctl->active = 0;
+      ctl->inv_gamma = ig;
+      ctl->mode = ctl->final_v ? kUpdVOnly : kUpdNone;
+      ctl->mode_iter = j;
+    }
+    return;
+  }
+
+  // ---- first sweep of the next vector ----------------------------------------
+  if (gs == 2) {
+    // Stephen's trick: r1 = [q/gamma ; beta/gamma^2 - (t/gamma)^T (q/gamma)]
+    for (int c = tid; c < j; c += blockDim.x) {
+      sr1[c] = Q[c] * ig;
+      sx[c] = st[c] * ig;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const double d = wave_dot(sx, sr1, j);
+      if (lane == 0) sr1[j] = beta * ig * ig - d;
+    }
+  } else {
+    // r1 = (I + L_{0:j+1,0:j+1})^{-1} [q/gamma ; beta/gamma^2]
+    for (int c = tid; c < j; c += blockDim.x) sx[c] = Q[c] * ig;
+    __syncthreads();
+    for (int i = wave; i < j; i += nw) {
+      const double* trow = w.T + (size_t)i * ldt;
+      double acc = 0.0;
+      for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], sx[c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) sr1[i] = acc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const double d = wave_dot(sl, sr1, j);
+      if (lane == 0) sr1[j] = beta * ig * ig - d;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i <= j; i += blockDim.x) {
+    w.coef_r1[i] = sr1[i];
+    if (i < j) w.coef_t[i] = st[i];
+  }
+  if (tid == 0) {
+    ctl->inv_gamma = ig;
+    ctl->gamma_prev = gamma;
+    ctl->mode = kUpdNormal;
+    ctl->mode_iter = j;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused reduction [V_{0:j}, u]^T [u, z] (+ small solve in the last block)
+// ---------------------------------------------------------------------------
+//
+// A block owns a contiguous row range.  Its 8 waves are arranged as Wc column
+// groups x Wr row slices: a wave accumulates 2*CPW sums (against u and z) for
+// its columns over its rows, so V is streamed exactly once and each wave
+// reduces across lanes only once per column group.
+
+struct ReduceShape {
+  int cpw, wc, wr, nblocks;
+  long long rows_per_block;
+};
+
+static ReduceShape reduce_shape(long long n, int ncol) {
+  ReduceShape s;
+  int cpw = 1;
+  const int want = (ncol + kReduceWaves - 1) / kReduceWaves;
+  while (cpw < want && cpw < 16) cpw *= 2;
+  const int nchunk = (ncol + cpw - 1) / cpw;
+  s.cpw = cpw;
+  s.wc = nchunk < kReduceWaves ? nchunk : kReduceWaves;
+  s.wr = kReduceWaves / s.wc;
+  long long nb = (n + 511) / 512;
+  if (nb > 512) nb = 512;
+  if (nb < 1) nb = 1;
+  long long rpb = (n + nb - 1) / nb;
+  rpb = (rpb + 63) / 64 * 64;
+  nb = (n + rpb - 1) / rpb;
+  s.nblocks = (int)nb;
+  s.rows_per_block = rpb;
+  return s;
+}
+
+int reduce_grid(long long n) { return reduce_shape(n, 1).nblocks; }
+
+template <int CPW>
+__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
+    Work w, long long n, int j, int with_z, long long rows_per_block, int wc, int wr,
+    const double* __restrict__ Vraw, long long ldv_raw, const double* __restrict__ zraw,
+    double* __restrict__ raw_out) {
+  extern __shared__ double lds[];
+  const bool raw = (raw_out != nullptr);
+  if (!raw && !ctl_active(w.ctl)) return;
+  const double* __restrict__ V = raw ? Vraw : w.V;
+  const long long ldv = raw ? ldv_raw : w.ldv;
+  const double* __restrict__ z = raw ? zraw : w.z;
+  const int ncol = j + 1;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const long long r0 = (long long)blockIdx.x * rows_per_block;
+  const long long r1 = min(n, r0 + rows_per_block);
+  const double* __restrict__ u = V + (size_t)j * ldv;
+  const int nchunk = (ncol + CPW - 1) / CPW;
+  const int cw = wave % wc;
+  const int rw = wave / wc;
+  if (rw < wr) {
+    for (int ch = cw; ch < nchunk; ch += wc) {
+      const int c0 = ch * CPW;
+      const int nc = min(CPW, ncol - c0);
+      double ap[CPW], aq[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
+      const double* __restrict__ vb = V + (size_t)c0 * ldv;
+      if (with_z) {
+        for (long long r = r0 + (long long)rw * kWave + lane; r < r1; r += (long long)wr * kWave) {
+          const double uu = u[r];
+          const double zz = z[r];
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            if (c < nc) {
+              const double v = vb[(size_t)c * ldv + r];
+              ap[c] = fma(v, uu, ap[c]);
+              aq[c] = fma(v, zz, aq[c]);
+            }
+          }
+        }
+      } else {
+        for (long long r = r0 + (long long)rw * kWave + lane; r < r1; r += (long long)wr * kWave) {
+          const double uu = u[r];
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            if (c < nc) ap[c] = fma(vb[(size_t)c * ldv + r], uu, ap[c]);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        if (c < nc) {
+          const double sp = wave_sum(ap[c]);
+          const double sq = wave_sum(aq[c]);
+          if (lane == 0) {
+            lds[(size_t)rw * 2 * ncol + c0 + c] = sp;
+            lds[(size_t)rw * 2 * ncol + ncol + c0 + c] = sq;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double* part = w.part + (size_t)blockIdx.x * w.pstride;
+  for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < wr; ++k) acc += lds[(size_t)k * 2 * ncol + v];
+    part[v] = acc;
+  }
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds)) return;
+  if (raw) {
+    for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) raw_out[v] = lds[v];
+    return;
+  }
+  small_solve(w, n, j, !with_z, lds, lds + ncol, lds + 2 * ncol);
+}
+
+static size_t reduce_lds_bytes(const ReduceShape& s, int ncol) {
+  size_t a = (size_t)s.wr * 2 * ncol;
+  size_t b = (size_t)2 * ncol + 7 * (size_t)(ncol + 2);
+  return (a > b ? a : b) * sizeof(double);
+}
+
+static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z,
+                                  const double* Vraw, long long ldv_raw, const double* zraw,
+                                  double* raw_out, hipStream_t s, int* nblocks_out) {
+  const int ncol = j + 1;
+  const ReduceShape sh = reduce_shape(n, ncol);
+  const size_t lds = reduce_lds_bytes(sh, ncol);
+  if (nblocks_out) *nblocks_out = sh.nblocks;
+  switch (sh.cpw) {
+#define IGS_RED_CASE(C)                                                                        \
+  case C:                                                                                      \
+    hipLaunchKernelGGL(reduce_kernel<C>, dim3(sh.nblocks), dim3(kReduceThreads), lds, s, w, n, \
+                       j, with_z ? 1 : 0, sh.rows_per_block, sh.wc, sh.wr, Vraw, ldv_raw, zraw, \
+                       raw_out);                                                               \
+    break;
+    IGS_RED_CASE(1) IGS_RED_CASE(2) IGS_RED_CASE(4) IGS_RED_CASE(8) IGS_RED_CASE(16)
+#undef IGS_RED_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,
+                         int* nblocks_out) {
+  return reduce_dispatch(w, n, j, with_z, nullptr, 0, nullptr, nullptr, s, nblocks_out);
+}
+
+hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j, const double* z,
+                             double* part, double* gpart, int pstride, unsigned* tickets,
+                             double* out, hipStream_t s) {
+  Work w{};
+  w.part = part;
+  w.gpart = gpart;
+  w.pstride = pstride;
+  w.tickets = tickets;
+  return reduce_dispatch(w, n, j, z != nullptr, V, ldv, z, out, s, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Basis update: one pass over V_{0:j}
+// ---------------------------------------------------------------------------
+
+template <bool HAS_T>
+__global__ __launch_bounds__(kUpdateThreads) void update_kernel(
+    Work w, long long n, int j, double* __restrict__ Vraw, long long ldv_raw,
+    const double* __restrict__ zraw, const double* __restrict__ traw,
+    const double* __restrict__ r1raw, double igraw, int raw) {
+  int mode;
+  double ig;
+  double* __restrict__ V;
+  long long ldv;
+  const double* __restrict__ z;
+  const double* __restrict__ t;
+  const double* __restrict__ r1;
+  if (raw) {
+    mode = kUpdNormal;
+    ig = igraw;
+    V = Vraw;
+    ldv = ldv_raw;
+    z = zraw;
+    t = traw;
+    r1 = r1raw;
+  } else {
+    if (load_agent(&w.ctl->mode_iter) != j) return;
+    mode = load_agent(&w.ctl->mode);
+    if (mode == kUpdNone) return;
+    ig = w.ctl->inv_gamma;
+    V = w.V;
+    ldv = w.ldv;
+    z = w.z;
+    t = w.coef_t;
+    r1 = w.coef_r1;
+  }
+  const bool need_r = (mode == kUpdNormal);
+  const bool fallback = (mode == kUpdFallback);
+  const double rj = need_r ? r1[j] : 0.0;
+  double* __restrict__ vj = V + (size_t)j * ldv;
+  double* __restrict__ un = V + (size_t)(j + 1) * ldv;
+  constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  double s2 = 0.0;  // ||w||^2 partial (fallback only)
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long base = tile * kTile + threadIdx.x;
+    double at[kUpdateRows], ar[kUpdateRows];
+#pragma unroll
+    for (int k = 0; k < kUpdateRows; ++k) at[k] = ar[k] = 0.0;
+    const bool full = base + (long long)(kUpdateRows - 1) * kUpdateThreads < n;
+    if (full) {
+      for (int c = 0; c < j; ++c) {
+        const double* __restrict__ vc = V + (size_t)c * ldv + base;
+        const double tc = HAS_T ? t[c] : 0.0;
+        const double rc = r1[c];
+#pragma unroll
+        for (int k = 0; k < kUpdateRows; ++k) {
+          const double v = vc[k * kUpdateThreads];
+          if (HAS_T) at[k] = fma(v, tc, at[k]);
+          ar[k] = fma(v, rc, ar[k]);
+        }
+      }
+    } else {
+      for (int c = 0; c < j; ++c) {
+        const double* __restrict__ vc = V + (size_t)c * ldv + base;
+        const double tc = HAS_T ? t[c] : 0.0;
+        const double rc = r1[c];
+#pragma unroll
+        for (int k = 0; k < kUpdateRows; ++k) {
+          if (base + k * kUpdateThreads < n) {
+            const double v = vc[k * kUpdateThreads];
+            if (HAS_T) at[k] = fma(v, tc, at[k]);
+            ar[k] = fma(v, rc, ar[k]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kUpdateRows; ++k) {
+      const long long r = base + k * kUpdateThreads;
+      if (r < n) {
+        if (fallback) {
+          const double wv = vj[r] - at[k];
+          vj[r] = wv;
+          s2 = fma(wv, wv, s2);
+        } else {
+          const double v = (vj[r] - at[k]) * ig;
+          vj[r] = v;
+          if (need_r) un[r] = z[r] * ig - ar[k] - v * rj;
+        }
+      }
+    }
+  }
+  if (!fallback) return;
+  // Lagged norm cancelled: w = u - V t is stored unnormalised; its explicit
+  // norm comes from a grid reduction and finishes column j-1.
+  __shared__ double red[kUpdateThreads / kWave];
+  __shared__ double tot[1];
+  s2 = wave_sum(s2);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int k = 0; k < kUpdateThreads / kWave; ++k) acc += red[k];
+    w.part[(size_t)blockIdx.x * w.pstride] = acc;
+  }
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 1, tot)) return;
+  const double gamma = sqrt(tot[0]);
+  // the group totals are consumed: reuse that global buffer as scratch
+  double* scratch = w.gpart;
+  double* hcol = scratch;
+  for (int i = threadIdx.x; i < j; i += blockDim.x) hcol[i] = w.H[(size_t)(j - 1) * w.ldh + i];
+  __syncthreads();
+  const int brk = finish_column(w, j, hcol, gamma, scratch + (j + 2), n);
+  if (threadIdx.x == 0) {
+    Ctl* c = w.ctl;
+    c->J = j;
+    c->active = 0;
+    c->fallbacks += 1;
+    if (brk) {
+      c->status = kBreakdown;
+      c->breakdowns += 1;
+    } else {
+      c->status = kLagnorm;
+    }
+    c->mode = kUpdNone;
+  }
+}
+
+// Tiles of kUpdateThreads * kUpdateRows rows; the grid is capped so that the
+// per-block partials of the fallback path fit the partial-sum buffer.
+static unsigned update_grid(long long n) {
+  const long long per = (long long)kUpdateThreads * kUpdateRows;
+  long long g = (n + per - 1) / per;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  return (unsigned)g;
+}
+
+hipError_t launch_update(const Work& w, long long n, int j, int gs, hipStream_t s) {
+  // With one Gauss-Seidel sweep there is no second-sweep vector t, and the
+  // kernel variant without it skips one FMA stream.
+  if (gs == 2) {
+    hipLaunchKernelGGL(update_kernel<true>, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w,
+                       n, j, nullptr, 0LL, nullptr, nullptr, nullptr, 0.0, 0);
+  } else {
+    hipLaunchKernelGGL(update_kernel<false>, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w,
+                       n, j, nullptr, 0LL, nullptr, nullptr, nullptr, 0.0, 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
+                             const double* t, const double* r1, double inv_gamma, hipStream_t s) {
+  Work w{};
+  hipLaunchKernelGGL(update_kernel<true>, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w, n,
+                     j, V, ldv, z, t, r1, inv_gamma, 1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// End of cycle: R y = g by back substitution (one block), then x += V y
+// ---------------------------------------------------------------------------
+
+// Panel width so that the right-hand side plus one panel of R stay within
+// 64 KiB of shared memory.
+static int lsq_panel(int m) {
+  if (m < 1) m = 1;
+  int p = (8000 - m) / m;
+  if (p > 32) p = 32;
+  if (p < 1) p = 1;
+  return p;
+}
+
+__global__ __launch_bounds__(256) void lsq_kernel(Work w, int panel) {
+  extern __shared__ double sm[];
+  const int J = load_agent(&w.ctl->J);
+  if (J <= 0) return;
+  double* sb = sm;               // right-hand side, updated in place
+  double* sp = sm + J + 1;       // panel of R: rows 0..hi-1, `panel` columns
+  for (int i = threadIdx.x; i < J; i += blockDim.x) sb[i] = w.g[i];
+  for (int hi = J; hi > 0; hi -= panel) {
+    const int lo = hi > panel ? hi - panel : 0;
+    const int pw = hi - lo;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < pw * hi; idx += blockDim.x) {
+      const int c = idx / hi;
+      const int i = idx % hi;
+      sp[(size_t)c * hi + i] = w.R[(size_t)(lo + c) * w.ldh + i];
+    }
+    __syncthreads();
+    for (int c = hi - 1; c >= lo; --c) {
+      const double* col = sp + (size_t)(c - lo) * hi;
+      const double yc = sb[c] / col[c];
+      __syncthreads();
+      for (int i = threadIdx.x; i < c; i += blockDim.x) sb[i] = fma(-col[i], yc, sb[i]);
+      if (threadIdx.x == 0) {
+        w.y[c] = yc;
+        sb[c] = yc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_lsq(const Work& w, int m, hipStream_t s) {
+  const int panel = lsq_panel(m);
+  const size_t lds = ((size_t)m + 1 + (size_t)panel * m) * sizeof(double);
+  hipLaunchKernelGGL(lsq_kernel, dim3(1), dim3(256), lds, s, w, panel);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long long n,
+                                                                double* __restrict__ x) {
+  const int J = load_agent(&w.ctl->J);
+  if (J <= 0) return;
+  const double* __restrict__ y = w.y;
+  constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long base = tile * kTile + threadIdx.x;
+    double acc[kUpdateRows];
+#pragma unroll
+    for (int k = 0; k < kUpdateRows; ++k) acc[k] = 0.0;
+    for (int c = 0; c < J; ++c) {
+      const double* __restrict__ vc = w.V + (size_t)c * w.ldv + base;
+      const double yc = y[c];
+#pragma unroll
+      for (int k = 0; k < kUpdateRows; ++k) {
+        if (base + k * kUpdateThreads < n) acc[k] = fma(vc[k * kUpdateThreads], yc, acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kUpdateRows; ++k) {
+      const long long r = base + k * kUpdateThreads;
+      if (r < n) x[r] += acc[k];
+    }
+  }
+}
+
+hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(xupdate_kernel, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w, n, x);
+  return hipGetLastError();
+}
+
+}  // namespace igs

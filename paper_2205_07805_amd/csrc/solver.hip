@@ -1,0 +1,677 @@
+// Host side of the C ABI (include/igs.h): contexts, workspace, the restarted
+// GMRES(m) driver and per-kernel event timing.  Every arithmetic step of the
+// solve runs in the kernels of kernels.hip; this file only validates input,
+// allocates, queues launches and reads one small control block per cycle.
+#include "../../include/igs.h"
+#include "igs_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <new>
+#include <string>
+#include <vector>
+
+using igs::Ctl;
+using igs::Op;
+using igs::Work;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct EventPair {
+  hipEvent_t a, b;
+  int kernel;
+  int j;        // iteration (-1: per cycle)
+  int cycle;
+  double bytes;
+};
+
+struct KStat {
+  int64_t launches = 0;
+  double ms = 0.0;
+  double bytes = 0.0;
+};
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+}  // namespace
+
+struct igs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  long long n = 0, nnz = 0;
+  Op op{};
+  int* d_row_ptr = nullptr;
+  int* d_col = nullptr;
+  double* d_vals = nullptr;
+  double* d_A = nullptr;
+
+  // workspace for restart length m_alloc
+  int m_alloc = 0;
+  Work w{};
+  Ctl* h_ctl = nullptr;  // pinned host copy of the control block
+
+  // raw step-kernel scratch
+  int raw_cols = 0;
+  double* raw_part = nullptr;
+  double* raw_gpart = nullptr;
+  unsigned* raw_tickets = nullptr;
+  double* raw_out = nullptr;
+  double* raw_t = nullptr;
+  double* raw_r1 = nullptr;
+
+  // first-cycle snapshot
+  std::vector<double> H_first;
+  int J_first = -1;
+  int ldh_first = 0;
+  double* d_V_first = nullptr;
+  size_t V_first_cols = 0;
+  int V_first_valid = 0;
+
+  // profiling
+  std::vector<hipEvent_t> event_pool;
+  size_t events_used = 0;
+  std::vector<EventPair> pending;
+  KStat stats[IGS_K_COUNT];
+
+  std::string err;
+};
+
+namespace {
+
+int set_err(igs_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_create_error = buf;
+  return code;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                                 \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      return set_err((ctx), e_ == hipErrorOutOfMemory ? IGS_ENOMEM : IGS_EDEVICE, "%s: %s",   \
+                     #call, hipGetErrorString(e_));                                            \
+    }                                                                                          \
+  } while (0)
+
+void free_workspace(igs_ctx* c) {
+  Work& w = c->w;
+  void* ptrs[] = {w.V, w.z, w.H, w.R, w.T, w.L, w.cs, w.sn, w.g, w.y, w.coef_t, w.coef_r1,
+                  w.part, w.gpart, w.tickets, w.ctl, c->d_V_first};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+  c->h_ctl = nullptr;
+  c->d_V_first = nullptr;
+  c->V_first_cols = 0;
+  c->w = Work{};
+  c->m_alloc = 0;
+}
+
+void free_raw(igs_ctx* c) {
+  void* ptrs[] = {c->raw_part, c->raw_gpart, c->raw_tickets, c->raw_out, c->raw_t, c->raw_r1};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  c->raw_part = c->raw_gpart = c->raw_out = c->raw_t = c->raw_r1 = nullptr;
+  c->raw_tickets = nullptr;
+  c->raw_cols = 0;
+}
+
+long long pick_ldv(long long n) {
+  long long ld = (n + 63) / 64 * 64;
+  if (ld % 4096 == 0) ld += 64;  // no large power-of-two stride between columns
+  return ld;
+}
+
+int ensure_workspace(igs_ctx* c, int m) {
+  if (c->m_alloc >= m) return IGS_OK;
+  free_workspace(c);
+  Work& w = c->w;
+  const long long n = c->n;
+  w.ldv = pick_ldv(n);
+  w.ldh = m + 1;
+  w.ldt = m + 1;
+  w.pstride = (2 * (m + 1) + 7) / 8 * 8;
+  if (w.pstride < 8) w.pstride = 8;
+  HIP_OR_FAIL(c, dalloc(&w.V, (size_t)w.ldv * (m + 1)));
+  HIP_OR_FAIL(c, dalloc(&w.z, (size_t)w.ldv));
+  HIP_OR_FAIL(c, dalloc(&w.H, (size_t)w.ldh * m));
+  HIP_OR_FAIL(c, dalloc(&w.R, (size_t)w.ldh * m));
+  HIP_OR_FAIL(c, dalloc(&w.T, (size_t)w.ldt * w.ldt));
+  HIP_OR_FAIL(c, dalloc(&w.L, (size_t)w.ldt * w.ldt));
+  HIP_OR_FAIL(c, dalloc(&w.cs, (size_t)m));
+  HIP_OR_FAIL(c, dalloc(&w.sn, (size_t)m));
+  HIP_OR_FAIL(c, dalloc(&w.g, (size_t)m + 1));
+  HIP_OR_FAIL(c, dalloc(&w.y, (size_t)m));
+  HIP_OR_FAIL(c, dalloc(&w.coef_t, (size_t)m + 2));
+  HIP_OR_FAIL(c, dalloc(&w.coef_r1, (size_t)m + 2));
+  HIP_OR_FAIL(c, dalloc(&w.part, (size_t)igs::kMaxBlocks * w.pstride));
+  HIP_OR_FAIL(c, dalloc(&w.gpart, (size_t)igs::kMaxGroups * w.pstride));
+  HIP_OR_FAIL(c, dalloc(&w.tickets, (size_t)igs::kMaxGroups + 1));
+  HIP_OR_FAIL(c, dalloc(&w.ctl, 1));
+  HIP_OR_FAIL(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_ctl), sizeof(Ctl),
+                               hipHostMallocDefault));
+  // Zero-fill at allocation, outside any captured work.
+  HIP_OR_FAIL(c, hipMemsetAsync(w.tickets, 0, sizeof(unsigned) * (igs::kMaxGroups + 1), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(w.ctl, 0, sizeof(Ctl), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(w.T, 0, sizeof(double) * w.ldt * w.ldt, c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(w.L, 0, sizeof(double) * w.ldt * w.ldt, c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(w.H, 0, sizeof(double) * w.ldh * m, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  memset(c->h_ctl, 0, sizeof(Ctl));
+  c->m_alloc = m;
+  return IGS_OK;
+}
+
+int ensure_raw(igs_ctx* c, int cols) {
+  if (c->raw_cols >= cols) return IGS_OK;
+  free_raw(c);
+  const int pstride = (2 * cols + 7) / 8 * 8;
+  HIP_OR_FAIL(c, dalloc(&c->raw_part, (size_t)igs::kMaxBlocks * pstride));
+  HIP_OR_FAIL(c, dalloc(&c->raw_gpart, (size_t)igs::kMaxGroups * pstride));
+  HIP_OR_FAIL(c, dalloc(&c->raw_tickets, (size_t)igs::kMaxGroups + 1));
+  HIP_OR_FAIL(c, dalloc(&c->raw_out, (size_t)2 * cols));
+  HIP_OR_FAIL(c, dalloc(&c->raw_t, (size_t)cols + 1));
+  HIP_OR_FAIL(c, dalloc(&c->raw_r1, (size_t)cols + 1));
+  HIP_OR_FAIL(c, hipMemsetAsync(c->raw_tickets, 0, sizeof(unsigned) * (igs::kMaxGroups + 1),
+                                c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->raw_cols = cols;
+  return IGS_OK;
+}
+
+// ---- profiling ------------------------------------------------------------
+
+hipEvent_t next_event(igs_ctx* c) {
+  if (c->events_used == c->event_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->event_pool.push_back(e);
+  }
+  return c->event_pool[c->events_used++];
+}
+
+struct Timed {
+  igs_ctx* c;
+  bool on;
+  EventPair p{};
+  Timed(igs_ctx* c_, bool on_, int kernel, int j, int cycle, double bytes) : c(c_), on(on_) {
+    if (!on) return;
+    p.a = next_event(c);
+    p.b = next_event(c);
+    p.kernel = kernel;
+    p.j = j;
+    p.cycle = cycle;
+    p.bytes = bytes;
+    if (p.a) (void)hipEventRecord(p.a, c->stream);
+  }
+  ~Timed() {
+    if (!on || !p.a || !p.b) return;
+    (void)hipEventRecord(p.b, c->stream);
+    c->pending.push_back(p);
+  }
+};
+
+// Did launch (kernel, j) of a cycle that ended after iteration j_end with
+// update mode `mode_end` do work?
+bool launch_ran(int kernel, int j, int j_end, int m, bool update_at_end) {
+  switch (kernel) {
+    case IGS_K_SPMV: return j <= j_end && j < m;
+    case IGS_K_REDUCE: return j <= j_end;
+    case IGS_K_UPDATE: return j < j_end || (j == j_end && update_at_end);
+    default: return true;
+  }
+}
+
+void harvest_cycle(igs_ctx* c, int cycle, int j_end, int m, bool update_at_end, bool xran) {
+  for (EventPair& p : c->pending) {
+    if (p.cycle != cycle) continue;
+    bool ran = launch_ran(p.kernel, p.j, j_end, m, update_at_end);
+    if (p.kernel == IGS_K_XUPDATE) ran = xran;
+    if (!ran) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
+    KStat& s = c->stats[p.kernel];
+    s.launches += 1;
+    s.ms += ms;
+    s.bytes += p.bytes;
+  }
+}
+
+int validate_csr(igs_ctx* c, long long n, long long nnz, const int32_t* rp, const int32_t* ci,
+                 const double* va) {
+  if (rp[0] != 0) return set_err(c, IGS_EINVAL, "row_ptr[0] = %d, expected 0", rp[0]);
+  for (long long i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return set_err(c, IGS_EINVAL, "row_ptr decreases at row %lld", i);
+  if ((long long)rp[n] != nnz)
+    return set_err(c, IGS_EINVAL, "row_ptr[n] = %d, expected nnz = %lld", rp[n], nnz);
+  for (long long k = 0; k < nnz; ++k) {
+    if (ci[k] < 0 || (long long)ci[k] >= n)
+      return set_err(c, IGS_EINVAL, "col_idx[%lld] = %d out of range", k, ci[k]);
+    if (!isfinite(va[k])) return set_err(c, IGS_EINVAL, "vals[%lld] is not finite", k);
+  }
+  return IGS_OK;
+}
+
+int common_create(igs_ctx** out, void* hip_stream, igs_ctx** made) {
+  if (!out) return set_err(nullptr, IGS_EINVAL, "out is NULL");
+  *out = nullptr;
+  igs_ctx* c = new (std::nothrow) igs_ctx();
+  if (!c) return set_err(nullptr, IGS_ENOMEM, "host allocation failed");
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return set_err(nullptr, IGS_EDEVICE, "no HIP device");
+  }
+  *made = c;
+  return IGS_OK;
+}
+
+int fail_create(igs_ctx* c, int code) {
+  g_create_error = c->err;
+  igs_destroy(c);
+  return code;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" int igs_create(igs_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                          const int32_t* col_idx, const double* vals, int ptrs_on_device,
+                          void* hip_stream) {
+  if (n < 1 || nnz < 0 || !row_ptr || (nnz > 0 && (!col_idx || !vals)))
+    return set_err(nullptr, IGS_EINVAL, "invalid size or NULL array");
+  if (n >= (1LL << 31) || nnz >= (1LL << 31))
+    return set_err(nullptr, IGS_EINVAL, "n and nnz must fit int32 indexing");
+  igs_ctx* c = nullptr;
+  int rc = common_create(out, hip_stream, &c);
+  if (rc != IGS_OK) return rc;
+  c->n = n;
+  c->nnz = nnz;
+  // host copies for validation (and staging of device input)
+  std::vector<int32_t> hrp, hci;
+  std::vector<double> hva;
+  const int32_t* rp = row_ptr;
+  const int32_t* ci = col_idx;
+  const double* va = vals;
+  if (ptrs_on_device) {
+    hrp.resize(n + 1);
+    hci.resize(nnz);
+    hva.resize(nnz);
+    if (hipMemcpy(hrp.data(), row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        (nnz > 0 && (hipMemcpy(hci.data(), col_idx, sizeof(int32_t) * nnz,
+                               hipMemcpyDeviceToHost) != hipSuccess ||
+                     hipMemcpy(hva.data(), vals, sizeof(double) * nnz, hipMemcpyDeviceToHost) !=
+                         hipSuccess))) {
+      set_err(c, IGS_EINVAL, "could not read the CSR arrays from device memory");
+      return fail_create(c, IGS_EINVAL);
+    }
+    rp = hrp.data();
+    ci = hci.data();
+    va = hva.data();
+  }
+  rc = validate_csr(c, n, nnz, rp, ci, va);
+  if (rc != IGS_OK) return fail_create(c, rc);
+  if (dalloc(&c->d_row_ptr, n + 1) != hipSuccess || dalloc(&c->d_col, nnz) != hipSuccess ||
+      dalloc(&c->d_vals, nnz) != hipSuccess) {
+    set_err(c, IGS_ENOMEM, "device allocation of the operator failed");
+    return fail_create(c, IGS_ENOMEM);
+  }
+  const hipMemcpyKind kind = ptrs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (hipMemcpy(c->d_row_ptr, row_ptr, sizeof(int32_t) * (n + 1), kind) != hipSuccess ||
+      (nnz > 0 && (hipMemcpy(c->d_col, col_idx, sizeof(int32_t) * nnz, kind) != hipSuccess ||
+                   hipMemcpy(c->d_vals, vals, sizeof(double) * nnz, kind) != hipSuccess))) {
+    set_err(c, IGS_EDEVICE, "copy of the operator to the device failed");
+    return fail_create(c, IGS_EDEVICE);
+  }
+  // lanes per row: the power of two at or above the mean row length
+  const double avg = (double)nnz / (double)n;
+  int lpr = 1;
+  while (lpr < 64 && (double)lpr < avg) lpr *= 2;
+  c->op.dense = 0;
+  c->op.n = n;
+  c->op.row_ptr = c->d_row_ptr;
+  c->op.col_idx = c->d_col;
+  c->op.vals = c->d_vals;
+  c->op.lpr = lpr;
+  *out = c;
+  return IGS_OK;
+}
+
+extern "C" int igs_create_dense(igs_ctx** out, int64_t n, const double* A, int64_t lda,
+                                int ptr_on_device, void* hip_stream) {
+  if (n < 1 || !A || lda < n) return set_err(nullptr, IGS_EINVAL, "invalid size or NULL array");
+  if (n >= (1LL << 31)) return set_err(nullptr, IGS_EINVAL, "n too large");
+  igs_ctx* c = nullptr;
+  int rc = common_create(out, hip_stream, &c);
+  if (rc != IGS_OK) return rc;
+  c->n = n;
+  c->nnz = n * n;
+  const long long ldd = (n + 63) / 64 * 64;
+  std::vector<double> host;
+  const double* src = A;
+  if (ptr_on_device) {
+    host.resize((size_t)n * lda);
+    if (hipMemcpy(host.data(), A, sizeof(double) * n * lda, hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      set_err(c, IGS_EINVAL, "could not read A from device memory");
+      return fail_create(c, IGS_EINVAL);
+    }
+    src = host.data();
+  }
+  for (long long i = 0; i < n; ++i)
+    for (long long k = 0; k < n; ++k)
+      if (!isfinite(src[i * lda + k])) {
+        set_err(c, IGS_EINVAL, "A[%lld, %lld] is not finite", i, k);
+        return fail_create(c, IGS_EINVAL);
+      }
+  if (dalloc(&c->d_A, (size_t)n * ldd) != hipSuccess) {
+    set_err(c, IGS_ENOMEM, "device allocation of A failed");
+    return fail_create(c, IGS_ENOMEM);
+  }
+  if (hipMemcpy2D(c->d_A, ldd * sizeof(double), src, lda * sizeof(double), n * sizeof(double), n,
+                  hipMemcpyHostToDevice) != hipSuccess) {
+    set_err(c, IGS_EDEVICE, "copy of A to the device failed");
+    return fail_create(c, IGS_EDEVICE);
+  }
+  c->op.dense = 1;
+  c->op.n = n;
+  c->op.A = c->d_A;
+  c->op.lda = ldd;
+  *out = c;
+  return IGS_OK;
+}
+
+extern "C" int igs_destroy(igs_ctx* c) {
+  if (!c) return IGS_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  free_workspace(c);
+  free_raw(c);
+  void* ptrs[] = {c->d_row_ptr, c->d_col, c->d_vals, c->d_A};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  delete c;
+  return IGS_OK;
+}
+
+extern "C" const char* igs_last_error(const igs_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" int igs_solve(igs_ctx* c, const double* b, double* x, int restart, double tol,
+                         int gs_iters, igs_info* info) {
+  return igs_solve_opts(c, b, x, restart, tol, gs_iters, nullptr, info);
+}
+
+extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restart, double tol,
+                              int gs_iters, const igs_opts* opts, igs_info* info) {
+  if (!c) return IGS_EINVAL;
+  c->err.clear();
+  if (!b || !x) return set_err(c, IGS_EINVAL, "b and x must be device pointers");
+  if ((reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(x)) % 16 != 0)
+    return set_err(c, IGS_EINVAL, "b and x must be 16-byte aligned");
+  if (restart < 1) return set_err(c, IGS_EINVAL, "restart must be >= 1");
+  if (!(tol >= 0.0) || !isfinite(tol)) return set_err(c, IGS_EINVAL, "tol must be finite, >= 0");
+  if (gs_iters != 1 && gs_iters != 2) return set_err(c, IGS_EINVAL, "gs_iters must be 1 or 2");
+  igs_opts o{};
+  if (opts) o = *opts;
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const long long n = c->n;
+  int m = restart;
+  if (m > n) m = (int)n;
+  if (m > IGS_MAX_RESTART) m = IGS_MAX_RESTART;
+  int rc = ensure_workspace(c, m);
+  if (rc != IGS_OK) return rc;
+  const long long maxit = o.maxit > 0 ? o.maxit : 20 * n;
+  const double tau = o.lagnorm_tau > 0.0 ? o.lagnorm_tau : 1e-4;
+  const bool prof = o.profile != 0;
+  const int final_v = o.final_basis_vector ? 1 : 0;
+  Work& w = c->w;
+  hipStream_t s = c->stream;
+  c->events_used = 0;
+  c->pending.clear();
+  c->J_first = -1;
+  c->V_first_valid = 0;
+
+  // ||b|| and the finiteness of b and x0
+  HIP_OR_FAIL(c, igs::launch_bnorm(b, x, n, w, s));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(c, hipStreamSynchronize(s));
+  if (c->h_ctl->nonfinite_in > 0)
+    return set_err(c, IGS_EINVAL, "b or x0 holds %d non-finite entries", c->h_ctl->nonfinite_in);
+  const double bnorm = c->h_ctl->bnorm;
+
+  // algorithmic bytes of each launch (minimum HBM traffic of its shape)
+  const double dn = (double)n;
+  const double op_bytes = c->op.dense ? 8.0 * dn * dn + 16.0 * dn
+                                      : 12.0 * (double)c->nnz + 4.0 * (dn + 1) + 16.0 * dn;
+
+  long long its = 0;
+  int cycles = 0;
+  int status = igs::kRunning;
+  int ret = IGS_ENOCONV;
+  double relres = NAN, arn = NAN;
+  bool converged = false;
+  bool final_check = false;
+  while (true) {
+    const long long its_before = its;
+    const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
+    {
+      Timed tm(c, prof, IGS_K_RESIDUAL, -1, cycles, op_bytes + 8.0 * dn);
+      HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w.V, w, its_before, maxit_cycle, m,
+                                          gs_iters, final_v, tol, tau, s));
+    }
+    const int jmax = final_check ? 0 : m;
+    for (int j = 0; j <= jmax; ++j) {
+      const double* u = w.V + (size_t)j * w.ldv;
+      if (j < m) {
+        Timed tm(c, prof, IGS_K_SPMV, j, cycles, op_bytes);
+        HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, w.z, w.ctl, s));
+      }
+      {
+        Timed tm(c, prof, IGS_K_REDUCE, j, cycles, 8.0 * dn * (j + 1) + (j < m ? 8.0 * dn : 0.0));
+        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, s, nullptr));
+      }
+      if (final_check) break;
+      // The tail update (j = m) is queued too: it finishes the last column
+      // when the lagged norm cancelled there, or writes v_m on request, and
+      // returns at once otherwise.  It never writes column m + 1.
+      {
+        Timed tm(c, prof, IGS_K_UPDATE, j, cycles, 8.0 * dn * (j + 1) + 8.0 * dn + 16.0 * dn);
+        HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_iters, s));
+      }
+    }
+    if (!final_check) {
+      HIP_OR_FAIL(c, igs::launch_lsq(w, m, s));
+      Timed tm(c, prof, IGS_K_XUPDATE, -1, cycles, 0.0);
+      HIP_OR_FAIL(c, igs::launch_xupdate(w, n, x, s));
+    }
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(c, hipStreamSynchronize(s));
+    const Ctl h = *c->h_ctl;
+    status = h.status;
+    const int J = h.J;
+    if (prof) {
+      int j_end = J;
+      if (status == igs::kNonfinite) j_end = J + 1;
+      const bool upd_end = (h.mode_iter == j_end) && (h.mode == igs::kUpdVOnly ||
+                                                      status == igs::kLagnorm);
+      // x-update bytes depend on J, known only now
+      for (EventPair& p : c->pending)
+        if (p.cycle == cycles && p.kernel == IGS_K_XUPDATE) p.bytes = 8.0 * dn * J + 16.0 * dn;
+      harvest_cycle(c, cycles, j_end, m, upd_end, J > 0);
+    }
+    if (cycles == 0 && !final_check) {
+      c->J_first = J;
+      c->ldh_first = w.ldh;
+      if (J > 0) {
+        c->H_first.assign((size_t)w.ldh * J, 0.0);
+        HIP_OR_FAIL(c, hipMemcpy(c->H_first.data(), w.H, sizeof(double) * w.ldh * J,
+                                 hipMemcpyDeviceToHost));
+      }
+      if (o.keep_first_basis) {
+        const size_t cols = (size_t)J + 1;
+        if (c->V_first_cols < cols) {
+          if (c->d_V_first) (void)hipFree(c->d_V_first);
+          c->d_V_first = nullptr;
+          c->V_first_cols = 0;
+          HIP_OR_FAIL(c, dalloc(&c->d_V_first, (size_t)w.ldv * cols));
+          c->V_first_cols = cols;
+        }
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->d_V_first, w.V, sizeof(double) * w.ldv * cols,
+                                      hipMemcpyDeviceToDevice, s));
+        HIP_OR_FAIL(c, hipStreamSynchronize(s));
+        c->V_first_valid = 1;
+      }
+    }
+    cycles += 1;
+    relres = bnorm > 0 ? h.rho / bnorm : h.rho;
+    if (status == igs::kConvStart) {
+      converged = true;
+      ret = IGS_OK;
+      break;
+    }
+    if (status == igs::kNonfinite) {
+      ret = set_err(c, IGS_ENUMERIC, "a non-finite value appeared in cycle %d", cycles);
+      its += J;
+      break;
+    }
+    if (final_check) {
+      ret = IGS_ENOCONV;
+      break;
+    }
+    its += J;
+    arn = bnorm > 0 ? h.gabs / bnorm : h.gabs;
+    if (J == 0) {
+      ret = set_err(c, IGS_ENUMERIC, "restart cycle %d made no progress", cycles);
+      break;
+    }
+    if (its >= maxit || (o.max_cycles > 0 && cycles >= o.max_cycles)) final_check = true;
+  }
+  if (info) {
+    info->iters = its;
+    info->cycles = cycles;
+    info->relres_true = relres;
+    info->arnoldi_relres = arn;
+    info->bnorm = bnorm;
+    info->converged = converged ? 1 : 0;
+    info->breakdowns = c->h_ctl->breakdowns;
+    info->lagnorm_fallbacks = c->h_ctl->fallbacks;
+    info->last_cycle_status = status;
+    info->first_cycle_J = c->J_first;
+    info->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (ret == IGS_ENOCONV) set_err(c, IGS_ENOCONV, "not converged after %lld iterations", its);
+  return ret;
+}
+
+extern "C" int igs_debug_copy_H(igs_ctx* c, double* H_host, int ldh, int* ncols) {
+  if (!c || !H_host || !ncols) return IGS_EINVAL;
+  if (c->J_first < 0) return set_err(c, IGS_EINVAL, "no solve has run");
+  const int J = c->J_first;
+  if (ldh < J + 1) return set_err(c, IGS_EINVAL, "ldh must be >= J + 1 = %d", J + 1);
+  for (int col = 0; col < J; ++col)
+    for (int i = 0; i <= J; ++i)
+      H_host[(size_t)col * ldh + i] = (i <= col + 1) ? c->H_first[(size_t)col * c->ldh_first + i] : 0.0;
+  *ncols = J;
+  return IGS_OK;
+}
+
+extern "C" int igs_debug_copy_V(igs_ctx* c, double* V_dev, int64_t ldv, int* ncols) {
+  if (!c || !V_dev || !ncols) return IGS_EINVAL;
+  if (!c->V_first_valid) return set_err(c, IGS_EINVAL, "solve with keep_first_basis = 1 first");
+  if (ldv < c->n) return set_err(c, IGS_EINVAL, "ldv must be >= n");
+  const int cols = c->J_first + 1;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipMemcpy2DAsync(V_dev, ldv * sizeof(double), c->d_V_first,
+                                  c->w.ldv * sizeof(double), c->n * sizeof(double), cols,
+                                  hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  *ncols = cols;
+  return IGS_OK;
+}
+
+extern "C" int igs_kernel_spmv(igs_ctx* c, const double* u, double* z) {
+  if (!c || !u || !z) return IGS_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, z, nullptr, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return IGS_OK;
+}
+
+extern "C" int igs_kernel_reduce(igs_ctx* c, const double* V, int64_t ldv, int j, const double* z,
+                                 double* P_host, double* Q_host) {
+  if (!c || !V || !P_host || j < 0 || j >= IGS_MAX_RESTART || ldv < c->n) return IGS_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  int rc = ensure_raw(c, j + 1);
+  if (rc != IGS_OK) return rc;
+  const int pstride = (2 * c->raw_cols + 7) / 8 * 8;
+  HIP_OR_FAIL(c, igs::launch_reduce_raw(V, ldv, c->n, j, z, c->raw_part, c->raw_gpart, pstride,
+                                        c->raw_tickets, c->raw_out, c->stream));
+  std::vector<double> out((size_t)2 * (j + 1));
+  HIP_OR_FAIL(c, hipMemcpyAsync(out.data(), c->raw_out, sizeof(double) * out.size(),
+                                hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k <= j; ++k) {
+    P_host[k] = out[k];
+    if (Q_host) Q_host[k] = out[(size_t)(j + 1) + k];
+  }
+  return IGS_OK;
+}
+
+extern "C" int igs_kernel_update(igs_ctx* c, double* V, int64_t ldv, int j, const double* z,
+                                 const double* t_host, const double* r1_host, double inv_gamma) {
+  if (!c || !V || !z || !r1_host || j < 0 || j >= IGS_MAX_RESTART || ldv < c->n)
+    return IGS_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  int rc = ensure_raw(c, j + 1);
+  if (rc != IGS_OK) return rc;
+  std::vector<double> tt((size_t)j + 1, 0.0);
+  if (t_host)
+    for (int k = 0; k < j; ++k) tt[k] = t_host[k];
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->raw_t, tt.data(), sizeof(double) * (j + 1),
+                                hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->raw_r1, r1_host, sizeof(double) * (j + 1),
+                                hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, igs::launch_update_raw(V, ldv, c->n, j, z, c->raw_t, c->raw_r1, inv_gamma,
+                                        c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return IGS_OK;
+}
+
+extern "C" int igs_profile_get(igs_ctx* c, int which, int64_t* launches, double* total_ms,
+                               double* total_bytes) {
+  if (!c || which < 0 || which >= IGS_K_COUNT) return IGS_EINVAL;
+  if (launches) *launches = c->stats[which].launches;
+  if (total_ms) *total_ms = c->stats[which].ms;
+  if (total_bytes) *total_bytes = c->stats[which].bytes;
+  return IGS_OK;
+}
+
+extern "C" int igs_profile_reset(igs_ctx* c) {
+  if (!c) return IGS_EINVAL;
+  for (KStat& s : c->stats) s = KStat{};
+  return IGS_OK;
+}

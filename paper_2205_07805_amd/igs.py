@@ -1,0 +1,194 @@
+"""ctypes binding of the C ABI in include/igs.h (argument marshalling only).
+
+Every function here forwards to the function of the same name in
+``libigs.so``; all arithmetic of the solve runs in the library's HIP kernels.
+Pointer arguments accept a torch tensor (its ``data_ptr()``), a numpy array
+(host memory) or a plain integer address.  Loading fails loudly when the
+library has not been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libigs.so")
+
+IGS_OK, IGS_ENOCONV, IGS_EINVAL, IGS_ENOMEM, IGS_EDEVICE, IGS_ENOTIMPL, IGS_ENUMERIC = 0, 1, -1, -2, -3, -4, -5
+IGS_MAX_RESTART = 512
+(IGS_K_SPMV, IGS_K_REDUCE, IGS_K_UPDATE, IGS_K_XUPDATE, IGS_K_RESIDUAL, IGS_K_COUNT) = range(6)
+KERNEL_NAMES = ("spmv", "reduce", "update", "xupdate", "residual")
+CYCLE_STATUS = ("running", "converged_at_start", "arnoldi_converged", "full", "breakdown",
+                "lagnorm", "maxit", "nonfinite")
+
+EXPORTED = (
+    "igs_create", "igs_create_dense", "igs_solve", "igs_solve_opts", "igs_destroy",
+    "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
+    "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
+)
+
+
+class IgsOpts(ctypes.Structure):
+    _fields_ = [("maxit", c_int64), ("lagnorm_tau", c_double), ("final_basis_vector", c_int),
+                ("profile", c_int), ("max_cycles", c_int), ("keep_first_basis", c_int),
+                ("reserved", c_int * 6)]
+
+
+class IgsInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int64), ("cycles", c_int64), ("relres_true", c_double),
+                ("arnoldi_relres", c_double), ("bnorm", c_double), ("converged", c_int),
+                ("breakdowns", c_int), ("lagnorm_fallbacks", c_int), ("last_cycle_status", c_int),
+                ("first_cycle_J", c_int), ("reserved", c_int), ("seconds", c_double)]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d["last_cycle_status"] = CYCLE_STATUS[self.last_cycle_status] \
+            if 0 <= self.last_cycle_status < len(CYCLE_STATUS) else self.last_cycle_status
+        return d
+
+
+class IgsError(RuntimeError):
+    def __init__(self, func: str, code: int, message: str):
+        super().__init__(f"{func} failed with code {code}: {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libigs.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2205_07805_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "igs_create": (c_int, [POINTER(P), c_int64, c_int64, P, P, P, c_int, P]),
+        "igs_create_dense": (c_int, [POINTER(P), c_int64, P, c_int64, c_int, P]),
+        "igs_solve": (c_int, [P, P, P, c_int, c_double, c_int, POINTER(IgsInfo)]),
+        "igs_solve_opts": (c_int, [P, P, P, c_int, c_double, c_int, POINTER(IgsOpts), POINTER(IgsInfo)]),
+        "igs_destroy": (c_int, [P]),
+        "igs_last_error": (ctypes.c_char_p, [P]),
+        "igs_debug_copy_H": (c_int, [P, P, c_int, POINTER(c_int)]),
+        "igs_debug_copy_V": (c_int, [P, P, c_int64, POINTER(c_int)]),
+        "igs_kernel_spmv": (c_int, [P, P, P]),
+        "igs_kernel_reduce": (c_int, [P, P, c_int64, c_int, P, P, P]),
+        "igs_kernel_update": (c_int, [P, P, c_int64, c_int, P, P, P, c_double]),
+        "igs_profile_get": (c_int, [P, c_int, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
+        "igs_profile_reset": (c_int, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(x) -> c_void_p:
+    """Address of a torch tensor, numpy array, ctypes object or integer."""
+    if x is None:
+        return c_void_p(None)
+    if hasattr(x, "data_ptr"):
+        return c_void_p(x.data_ptr())
+    if hasattr(x, "ctypes"):
+        return c_void_p(x.ctypes.data)
+    if isinstance(x, c_void_p):
+        return x
+    return c_void_p(int(x))
+
+
+def _check(func: str, rc: int, ctx=None, allow=(IGS_OK,)):
+    if rc in allow:
+        return rc
+    msg = load_library().igs_last_error(ctx)
+    raise IgsError(func, rc, msg.decode() if msg else "")
+
+
+def igs_create(n, nnz, row_ptr, col_idx, vals, ptrs_on_device, hip_stream=None) -> c_void_p:
+    lib = load_library()
+    ctx = c_void_p()
+    rc = lib.igs_create(ctypes.byref(ctx), int(n), int(nnz), _ptr(row_ptr), _ptr(col_idx),
+                        _ptr(vals), int(ptrs_on_device), _ptr(hip_stream))
+    _check("igs_create", rc)
+    return ctx
+
+
+def igs_create_dense(n, A, lda, ptr_on_device, hip_stream=None) -> c_void_p:
+    lib = load_library()
+    ctx = c_void_p()
+    rc = lib.igs_create_dense(ctypes.byref(ctx), int(n), _ptr(A), int(lda), int(ptr_on_device),
+                              _ptr(hip_stream))
+    _check("igs_create_dense", rc)
+    return ctx
+
+
+def igs_solve(ctx, b, x, restart, tol, gs_iters):
+    """Returns (return code, info dict); raises on negative codes."""
+    info = IgsInfo()
+    rc = load_library().igs_solve(ctx, _ptr(b), _ptr(x), int(restart), float(tol), int(gs_iters),
+                                  ctypes.byref(info))
+    _check("igs_solve", rc, ctx, allow=(IGS_OK, IGS_ENOCONV))
+    return rc, info.as_dict()
+
+
+def igs_solve_opts(ctx, b, x, restart, tol, gs_iters, opts: IgsOpts | None = None):
+    info = IgsInfo()
+    rc = load_library().igs_solve_opts(ctx, _ptr(b), _ptr(x), int(restart), float(tol),
+                                       int(gs_iters), ctypes.byref(opts) if opts else None,
+                                       ctypes.byref(info))
+    _check("igs_solve_opts", rc, ctx, allow=(IGS_OK, IGS_ENOCONV))
+    return rc, info.as_dict()
+
+
+def igs_destroy(ctx) -> int:
+    return load_library().igs_destroy(ctx)
+
+
+def igs_last_error(ctx=None) -> str:
+    msg = load_library().igs_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def igs_debug_copy_H(ctx, H_host, ldh) -> int:
+    ncols = c_int()
+    _check("igs_debug_copy_H", load_library().igs_debug_copy_H(ctx, _ptr(H_host), int(ldh),
+                                                               ctypes.byref(ncols)), ctx)
+    return ncols.value
+
+
+def igs_debug_copy_V(ctx, V_dev, ldv) -> int:
+    ncols = c_int()
+    _check("igs_debug_copy_V", load_library().igs_debug_copy_V(ctx, _ptr(V_dev), int(ldv),
+                                                               ctypes.byref(ncols)), ctx)
+    return ncols.value
+
+
+def igs_kernel_spmv(ctx, u, z) -> None:
+    _check("igs_kernel_spmv", load_library().igs_kernel_spmv(ctx, _ptr(u), _ptr(z)), ctx)
+
+
+def igs_kernel_reduce(ctx, V, ldv, j, z, P_host, Q_host) -> None:
+    _check("igs_kernel_reduce", load_library().igs_kernel_reduce(
+        ctx, _ptr(V), int(ldv), int(j), _ptr(z), _ptr(P_host), _ptr(Q_host)), ctx)
+
+
+def igs_kernel_update(ctx, V, ldv, j, z, t_host, r1_host, inv_gamma) -> None:
+    _check("igs_kernel_update", load_library().igs_kernel_update(
+        ctx, _ptr(V), int(ldv), int(j), _ptr(z), _ptr(t_host), _ptr(r1_host),
+        float(inv_gamma)), ctx)
+
+
+def igs_profile_get(ctx, which):
+    n, ms, by = c_int64(), c_double(), c_double()
+    _check("igs_profile_get", load_library().igs_profile_get(
+        ctx, int(which), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)), ctx)
+    return n.value, ms.value, by.value
+
+
+def igs_profile_reset(ctx) -> None:
+    _check("igs_profile_reset", load_library().igs_profile_reset(ctx), ctx)

@@ -1,0 +1,95 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports every symbol
+declared in include/igs.h, and the ctypes structures match the C layout.
+No compute calls (there is no GPU here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "igs.h")
+LIB = os.path.join(ROOT, "paper_2205_07805_amd", "libigs.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(igs_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2205_07805_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("igs_create", "igs_create_dense", "igs_solve", "igs_destroy",
+                     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2205_07805_amd import igs
+    assert sorted(igs.EXPORTED) == declared_functions()
+    for name in declared_functions():
+        assert callable(getattr(igs, name)), name
+
+
+def test_struct_layout_matches_c(tmp_path):
+    """Compile a C probe against the header and compare sizes/offsets with ctypes."""
+    from paper_2205_07805_amd.igs import IgsInfo, IgsOpts
+    src = tmp_path / "probe.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "igs.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(igs_opts), offsetof(igs_opts, lagnorm_tau),
+         offsetof(igs_opts, keep_first_basis), sizeof(igs_info), offsetof(igs_info, seconds));
+  printf("%d %d\n", IGS_MAX_RESTART, IGS_K_COUNT);
+  return 0;
+}
+''')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == ctypes.sizeof(IgsOpts)
+    assert vals[1] == IgsOpts.lagnorm_tau.offset
+    assert vals[2] == IgsOpts.keep_first_basis.offset
+    assert vals[3] == ctypes.sizeof(IgsInfo)
+    assert vals[4] == IgsInfo.seconds.offset
+    from paper_2205_07805_amd import igs
+    assert vals[5] == igs.IGS_MAX_RESTART and vals[6] == igs.IGS_K_COUNT
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2205_07805_amd import igs
+    with pytest.raises(RuntimeError, match="missing"):
+        saved = igs._lib
+        igs._lib = None
+        try:
+            igs.load_library(str(tmp_path / "nope.so"))
+        finally:
+            igs._lib = saved
+
+
+def test_create_rejects_bad_input_without_gpu_work(lib):
+    """Argument validation happens before any device call."""
+    from paper_2205_07805_amd import igs
+    igs.load_library()
+    ctx = ctypes.c_void_p()
+    rc = igs.load_library().igs_create(ctypes.byref(ctx), 0, 0, None, None, None, 0, None)
+    assert rc == igs.IGS_EINVAL and not ctx.value
+    assert "invalid" in igs.igs_last_error(None)

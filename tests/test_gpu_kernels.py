@@ -1,0 +1,163 @@
+"""GPU parity of each hot-path step kernel against the oracle's step functions,
+called through the C ABI on seeded inputs with ragged, multi-block sizes."""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.arnoldi as OA
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _ctx_csr(a):
+    from paper_2205_07805_amd import igs
+    return igs.igs_create(a.n, a.nnz, a.row_ptr, a.col_idx, a.vals, 0, None)
+
+
+def _random_csr(n, avg, seed, empty_rows=()):
+    rng = np.random.default_rng(seed)
+    counts = rng.poisson(avg, n)
+    counts[list(empty_rows)] = 0
+    counts = np.minimum(counts, n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    cols = np.concatenate([np.sort(rng.choice(n, c, replace=False)) for c in counts]).astype(np.int32)
+    vals = rng.standard_normal(cols.size)
+    return W.Csr(n, row_ptr.astype(np.int32), cols, vals)
+
+
+CSR_CASES = {
+    "convdiff3d_17": lambda: W.convdiff3d(17, 50.0),
+    "convdiff2d_31": lambda: W.convdiff2d(31, 10.0),
+    "random_short_rows_empty": lambda: _random_csr(3001, 3.0, 1, empty_rows=(0, 17, 3000)),
+    "random_long_rows": lambda: _random_csr(1500, 40.0, 2),
+    "single_row": lambda: W.csr_from_dense(np.array([[2.5]])),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CSR_CASES))
+def test_spmv_csr_matches_oracle(torch, case):
+    from paper_2205_07805_amd import igs
+    a = CSR_CASES[case]()
+    print(f"spmv csr case={case} n={a.n} nnz={a.nnz}", flush=True)
+    ctx = _ctx_csr(a)
+    try:
+        u = W.rhs_normal(a.n, 7)
+        ud = torch.tensor(u, device="cuda")
+        zd = torch.empty_like(ud)
+        igs.igs_kernel_spmv(ctx, ud, zd)
+        ref = O.as_operator(a).matvec(u)
+        scale = np.abs(a.vals).max() * np.abs(u).max() * max(1, np.diff(a.row_ptr).max())
+        np.testing.assert_allclose(zd.cpu().numpy(), ref, rtol=0, atol=1e-14 * scale)
+    finally:
+        igs.igs_destroy(ctx)
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000, 1001])
+def test_gemv_dense_matches_oracle(torch, n):
+    from paper_2205_07805_amd import igs
+    a = W.random_wellcond(n, 3) if n > 1 else np.array([[3.0]])
+    print(f"gemv dense n={n}", flush=True)
+    ctx = igs.igs_create_dense(n, a, n, 0, None)
+    try:
+        u = W.rhs_normal(n, 8)
+        ud = torch.tensor(u, device="cuda")
+        zd = torch.empty_like(ud)
+        igs.igs_kernel_spmv(ctx, ud, zd)
+        ref = O.as_operator(a).matvec(u)
+        np.testing.assert_allclose(zd.cpu().numpy(), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+    finally:
+        igs.igs_destroy(ctx)
+
+
+_CTX = {}
+
+
+def ctx_of_size(n):
+    """A context whose n matches the step-kernel buffers (the operator is unused)."""
+    if n not in _CTX:
+        _CTX[n] = _ctx_csr(W.csr_from_dense(np.eye(1)) if n == 1 else
+                           W.Csr(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+                                 np.ones(n)))
+    return _CTX[n]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _release_contexts():
+    yield
+    from paper_2205_07805_amd import igs
+    for ctx in _CTX.values():
+        igs.igs_destroy(ctx)
+    _CTX.clear()
+
+
+def _basis(torch, n, ncols, seed, ldv=None):
+    """Random near-orthonormal columns (as a Krylov basis would be) plus an
+    arbitrary last column, stored column-major with leading dimension ldv."""
+    ldv = ldv or n
+    rng = np.random.default_rng(seed)
+    Vt = rng.standard_normal((ncols, n)) / np.sqrt(n)
+    host = np.zeros((ncols, ldv))
+    host[:, :n] = Vt
+    return Vt, torch.tensor(host, device="cuda")
+
+
+@pytest.mark.parametrize("j", [0, 1, 5, 8, 15, 16, 17, 31, 60, 127, 200])
+@pytest.mark.parametrize("n", [100_003, 4_099])
+def test_reduce_matches_oracle(torch, n, j):
+    from paper_2205_07805_amd import igs
+    print(f"reduce n={n} j={j}", flush=True)
+    ctx_small = ctx_of_size(n)
+    ldv = n + 13
+    Vt, Vd = _basis(torch, n, j + 1, seed=j + n, ldv=ldv)
+    z = W.rhs_normal(n, j)
+    zd = torch.tensor(z, device="cuda")
+    P = np.zeros(j + 1)
+    Q = np.zeros(j + 1)
+    igs.igs_kernel_reduce(ctx_small, Vd, ldv, j, zd, P, Q)
+    p, alpha, q, beta = OA.one_reduction(Vt[:j], Vt[j], z)
+    Pref = np.concatenate([p, [alpha]])
+    Qref = np.concatenate([q, [beta]])
+    tol_p = 1e-14 * np.sqrt(n) * np.linalg.norm(Vt, axis=1) * np.linalg.norm(Vt[j])
+    tol_q = 1e-14 * np.sqrt(n) * np.linalg.norm(Vt, axis=1) * np.linalg.norm(z)
+    assert np.all(np.abs(P - Pref) <= tol_p)
+    assert np.all(np.abs(Q - Qref) <= tol_q)
+    # without z (the tail iteration)
+    P2 = np.zeros(j + 1)
+    igs.igs_kernel_reduce(ctx_small, Vd, ldv, j, None, P2, None)
+    assert np.array_equal(P2, P)
+
+
+@pytest.mark.parametrize("j", [0, 1, 7, 33, 60])
+@pytest.mark.parametrize("n", [100_003, 1_025])
+def test_update_matches_oracle(torch, n, j):
+    from paper_2205_07805_amd import igs
+    print(f"update n={n} j={j}", flush=True)
+    ctx_small = ctx_of_size(n)
+    ldv = n + 3
+    Vt, Vd = _basis(torch, n, j + 2, seed=3 * j + n, ldv=ldv)
+    rng = np.random.default_rng(j)
+    t = rng.standard_normal(j) * 1e-3
+    r1 = rng.standard_normal(j + 1)
+    gamma = 0.37
+    z = W.rhs_normal(n, 100 + j)
+    zd = torch.tensor(z, device="cuda")
+    igs.igs_kernel_update(ctx_small, Vd, ldv, j, zd, t if j else None, r1, 1.0 / gamma)
+    out = Vd.cpu().numpy()
+    vj = OA.normalise_after_second_sweep(Vt[:j], Vt[j], t, gamma)
+    Vnew = np.vstack([Vt[:j], vj[None, :]])
+    un = OA.first_sweep_next(Vnew, z, gamma, r1)
+    np.testing.assert_allclose(out[j, :n], vj, rtol=0, atol=1e-13 * np.abs(vj).max())
+    np.testing.assert_allclose(out[j + 1, :n], un, rtol=0, atol=1e-13 * np.abs(un).max())
+    # untouched: the other columns and the padding
+    np.testing.assert_array_equal(out[:j, :n], Vt[:j])
+    assert np.all(out[:, n:] == 0.0)
