@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the one-reduction IGS-GMRES solver on one MI355X.
+
+Workload: 3D convection-diffusion, 7-point upwind stencil on a 128^3 grid
+(n = 2,097,152, 14,581,760 nonzeros, CSR FP64), wind (1,1,1) * Pe with
+Pe = 50, b ~ N(0,1) seed 0, x0 = 0, GMRES(60), two Gauss-Seidel sweeps,
+tol 1e-10.  One step = one full solve to tolerance (every restart cycle, with
+the operator apply, the fused reduction, the small solve, the basis update,
+the least-squares solve and x = x0 + V y).
+
+Prints ONE JSON line: Arnoldi iterations per second over the timed solves,
+the achieved algorithmic HBM bandwidth, the roofline of the dominant kernel
+(bytes per launch over its HIP-event duration on the solver's stream), the
+same solve with one Gauss-Seidel sweep, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Arnoldi iters/s + HBM GB/s; batched solves/s, p50/p99 latency at β≤1e-12"
+KERNEL_SRC = os.path.join(ROOT, "paper_2205_07805_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_sha() or t.get("workload") != workload:
+        return None
+    return t.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+
+
+def backward_error_torch(torch, a, b_d, x_d, iters=60):
+    """beta(x) = ||b - A x|| / (||b|| + ||A||_2 ||x||), with torch's own sparse
+    product (not the solver's kernels) and a power-iteration estimate of
+    ||A||_2 (a lower bound, so beta is conservative)."""
+    dev = b_d.device
+    A = torch.sparse_csr_tensor(torch.as_tensor(a.row_ptr.astype(np.int64), device=dev),
+                                torch.as_tensor(a.col_idx.astype(np.int64), device=dev),
+                                torch.as_tensor(a.vals, device=dev), size=(a.n, a.n))
+    At = A.to_sparse_coo().t().coalesce().to_sparse_csr()
+    r = b_d - (A @ x_d.unsqueeze(1)).squeeze(1)
+    g = torch.Generator(device=dev).manual_seed(1234)
+    v = torch.randn(a.n, device=dev, dtype=torch.float64, generator=g)
+    v /= v.norm()
+    est = 0.0
+    for _ in range(iters):
+        w = (At @ (A @ v.unsqueeze(1))).squeeze(1)
+        nw = float(w.norm())
+        est = nw ** 0.5
+        v = w / nw
+    return float(r.norm()) / (float(b_d.norm()) + est * float(x_d.norm())), est
+
+
+def cpu_baseline(a, b, restart, n_iters):
+    """The FP64 oracle (one-reduce cycle) on the host, first n_iters iterations."""
+    import oracle
+    from oracle.arnoldi import StopRule, cycle_igs_1r
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads") or 1) for i in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        threads = os.cpu_count()
+    op = oracle.as_operator(a)
+    r0 = b.copy()
+    t0 = time.perf_counter()
+    cyc = cycle_igs_1r(op, r0, restart, StopRule(tol_abs=0.0, its_left=n_iters))
+    dt = time.perf_counter() - t0
+    return {"value": cyc.J / dt, "unit": "Arnoldi iters/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"first {cyc.J} Arnoldi iterations (one-reduce, two sweeps) of one "
+                      f"GMRES({restart}) cycle on the same {a.n}-row system, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--restart", type=int, default=60)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=24)
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2205_07805_amd import Solver, igs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    a, b = W.make_convdiff3d(args.grid, 50.0)
+    log(f"[bench] generated n={a.n} nnz={a.nnz} in {time.perf_counter() - t0:.1f}s")
+    workload = f"convdiff3d_N{args.grid}_Pe50_gmres{args.restart}_tol{args.tol:g}"
+
+    s = Solver(a)
+    b_d = torch.as_tensor(b, device=dev)
+    x_d = torch.zeros_like(b_d)
+    opts = {} if args.no_profile else {"profile": 1}
+
+    def solve(gs):
+        x_d.zero_()
+        with torch.cuda.stream(s.stream):
+            return igs.igs_solve_opts(s.ctx, b_d, x_d, args.restart, args.tol, gs,
+                                      igs.IgsOpts(**opts))
+
+    for _ in range(args.warmup):
+        rc, info = solve(2)
+        log(f"[bench] warmup: rc={rc} iters={info['iters']} relres={info['relres_true']:.2e}")
+    s.profile_reset()
+    torch.cuda.synchronize()
+    iters = 0
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        rc, info = solve(2)
+        iters += info["iters"]
+        if rc != 0:
+            raise RuntimeError(f"solve did not converge: {info}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = s.profile()
+    log(f"[bench] timed {args.steps} solves: {elapsed:.3f}s, {iters} iterations")
+
+    beta, anorm_est = backward_error_torch(torch, a, b_d, x_d)
+    info2 = info
+
+    # per-kernel figures from the HIP events of the timed region
+    kern = {}
+    for name, (launches, ms, by) in prof.items():
+        if launches:
+            kern[name] = {"launches": launches, "ms": ms, "avg_us": 1e3 * ms / launches,
+                          "GBs": by / (ms * 1e6) if ms > 0 else None, "bytes": by}
+    total_bytes = sum(k["bytes"] for k in kern.values())
+    dominant = max(("spmv", "reduce", "update"), key=lambda k: kern.get(k, {}).get("ms", 0.0))
+    dk = kern.get(dominant, {})
+    achieved = dk.get("GBs")
+    traffic = measured_traffic(dominant, workload)
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": traffic,
+                "avg_launch_us": dk.get("avg_us"),
+                "algorithmic_bytes_per_launch": dk["bytes"] / dk["launches"] if dk else None}
+
+    # the same solve with one Gauss-Seidel sweep (not timed into value)
+    rc1, info1 = solve(1)
+    t1 = time.perf_counter()
+    rc1, info1 = solve(1)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        cpu = cpu_baseline(a, b, args.restart, args.cpu_iters)
+        log(f"[bench] cpu baseline: {cpu['value']:.2f} iters/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": iters / elapsed,
+        "unit": "Arnoldi iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": a.n, "nnz": a.nnz, "restart": args.restart,
+                   "tol": args.tol, "gs_iters": 2, "x0": "zeros", "rhs": "N(0,1) seed 0",
+                   "parallelism": "single GPU"},
+        "iters_per_solve": iters / args.steps,
+        "hbm_GBs_algorithmic": total_bytes / elapsed / 1e9,
+        "backward_error": beta,
+        "anorm2_estimate": anorm_est,
+        "relres_true": info2["relres_true"],
+        "kernels": {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
+                        "GBs": round(v["GBs"], 1) if v["GBs"] else None} for k, v in kern.items()},
+        "roofline": roofline,
+        "gs1": {"iters": info1["iters"], "seconds": dt1, "iters_per_s": info1["iters"] / dt1,
+                "converged": bool(info1["converged"])},
+        "cpu_baseline": cpu,
+        "profiled": not args.no_profile,
+    }
+    s.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,6 +20,8 @@
 
 namespace igs {
 
+constexpr int LPR_RPG_MAX = 4;  // rows per lane group for rows of <= 8 lanes
+
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
@@ -44,51 +46,75 @@ __device__ __forceinline__ long long xcd_block(int b, int nb) {
   return (long long)(b % 8) * (nb / 8) + b / 8;
 }
 
-// Deterministic grid-wide sum of nv per-block values.
-// Every block calls this after writing part[blockIdx.x * pstride + v], v < nv.
-// Blocks are combined in groups of kGroup (the last block of a group sums its
-// group), then the last group sums the group totals.  Returns true in exactly
-// one block, in which out[v] (shared memory) then holds the total.
-__device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
-                                 int nv, double* out) {
-  __shared__ int s_last;
-  const int nb = gridDim.x;
-  const int b = blockIdx.x;
-  const int ngroups = (nb + kGroup - 1) / kGroup;
-  const int g = b / kGroup;
-  const int gsize = min(kGroup, nb - g * kGroup);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&tickets[g], 1u);
-    s_last = (prev == (unsigned)(gsize - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+// Fixed-order sum of `cnt` rows (row stride pstride) of nv values into out[v],
+// by all threads of the block.  Each thread sums a strided slice of the rows
+// with its loads issued in batches of eight before it adds, so the whole sum
+// costs about one memory latency.  scratch must hold max(blockDim.x, nv)
+// doubles; out and scratch are shared memory.
+__device__ void sum_rows(const double* src, int pstride, int cnt, int nv, double* out,
+                         double* scratch) {
+  const int nt = blockDim.x;
+  int S = nt / nv;
+  if (S < 1) S = 1;
+  if (S > 8) S = 8;
+  for (int t = threadIdx.x; t < S * nv; t += nt) {
+    const int v = t % nv;
+    const int sl = t / nv;
     double acc = 0.0;
-    const double* p = part + (size_t)g * kGroup * pstride + v;
-    for (int k = 0; k < gsize; ++k) acc += p[(size_t)k * pstride];
-    gpart[(size_t)g * pstride + v] = acc;
+    int k = sl;
+    for (; k + 7 * S < cnt; k += 8 * S) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = src[(size_t)(k + u * S) * pstride + v];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += a[u];
+    }
+    for (; k < cnt; k += S) acc += src[(size_t)k * pstride + v];
+    scratch[sl * nv + v] = acc;
   }
-  if (threadIdx.x == 0) tickets[g] = 0u;
-  __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&tickets[kMaxGroups], 1u);
-    s_last = (prev == (unsigned)(ngroups - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+  for (int v = threadIdx.x; v < nv; v += nt) {
     double acc = 0.0;
-    for (int k = 0; k < ngroups; ++k) acc += gpart[(size_t)k * pstride + v];
+    for (int sl = 0; sl < S; ++sl) acc += scratch[sl * nv + v];
     out[v] = acc;
   }
-  if (threadIdx.x == 0) tickets[kMaxGroups] = 0u;
   __syncthreads();
+}
+
+// Deterministic grid-wide sum of nv per-block values.
+// Precondition: wave 0 of every block has written its block's values to
+// part[blockIdx.x * pstride + v], v < nv (only wave 0 writes, so that its one
+// release fence publishes all of them).  Blocks are combined in groups of
+// kGroup -- the last block of a group to arrive sums that group -- and the
+// last group sums the group totals.  Returns true in exactly one block; there
+// out[v] (shared memory) holds the totals.  scratch: shared memory of
+// max(blockDim.x, nv) doubles, disjoint from out.
+__device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
+                                 int nv, double* out, double* scratch) {
+  __shared__ int s_last;
+  const int nb = gridDim.x;
+  const int g = blockIdx.x / kGroup;
+  const int ngroups = (nb + kGroup - 1) / kGroup;
+  const int gsize = min(kGroup, nb - g * kGroup);
+  if (threadIdx.x < kWave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) s_last = (atomicAdd(&tickets[g], 1u) == (unsigned)(gsize - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  sum_rows(part + (size_t)g * kGroup * pstride, pstride, gsize, nv, out, scratch);
+  if (threadIdx.x < kWave) {
+    for (int v = threadIdx.x; v < nv; v += kWave) gpart[(size_t)g * pstride + v] = out[v];
+    if (threadIdx.x == 0) tickets[g] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) s_last = (atomicAdd(&tickets[kMaxGroups], 1u) == (unsigned)(ngroups - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  sum_rows(gpart, pstride, ngroups, nv, out, scratch);
+  if (threadIdx.x == 0) tickets[kMaxGroups] = 0u;
   return true;
 }
 
@@ -105,9 +131,12 @@ __device__ __forceinline__ double wave_dot(const double* a, const double* b, int
 // operator apply: z = A u  (or r = b - A x)
 // ---------------------------------------------------------------------------
 
-// CSR with LPR lanes per row: the lanes of a row read its entries as one
-// contiguous, coalesced segment and combine them with a butterfly.
-template <int LPR>
+// CSR with LPR lanes per row and RPG consecutive rows per lane group.  The
+// lanes of a row read its entries as one contiguous, coalesced segment; the
+// row bounds, the first LPR entries of every row of the group and the x
+// gathers are each issued as one batch, so a group pays about three memory
+// latencies for RPG rows.  Rows longer than LPR finish in a strided loop.
+template <int LPR, int RPG>
 __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* __restrict__ rp,
                                                        const int* __restrict__ ci,
                                                        const double* __restrict__ va,
@@ -117,16 +146,50 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
                                                        const Ctl* __restrict__ gate) {
   if (gate != nullptr && !ctl_active(gate)) return;
   const long long lb = xcd_block(blockIdx.x, gridDim.x);
-  const long long row = (lb * blockDim.x + threadIdx.x) / LPR;
+  const long long grp = (lb * blockDim.x + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  if (row >= n) return;  // the LPR lanes of a row leave together
-  const int s = rp[row];
-  const int e = rp[row + 1];
-  double acc = 0.0;
-  for (int k = s + lane; k < e; k += LPR) acc = fma(va[k], x[ci[k]], acc);
+  const long long row0 = grp * RPG;
+  if (row0 >= n) return;  // the LPR lanes of a group leave together
+  int bnd[RPG + 1];
 #pragma unroll
-  for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
-  if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
+  for (int q = 0; q <= RPG; ++q) bnd[q] = rp[min(row0 + q, n)];
+  int cidx[RPG];
+  double val[RPG];
+#pragma unroll
+  for (int q = 0; q < RPG; ++q) {
+    const int k = bnd[q] + lane;
+    const bool ok = k < bnd[q + 1];
+    cidx[q] = ok ? ci[k] : 0;
+    val[q] = ok ? va[k] : 0.0;
+  }
+  double acc[RPG];
+#pragma unroll
+  for (int q = 0; q < RPG; ++q) acc[q] = val[q] * x[cidx[q]];
+#pragma unroll
+  for (int q = 0; q < RPG; ++q)
+    for (int k = bnd[q] + lane + LPR; k < bnd[q + 1]; k += LPR) acc[q] = fma(va[k], x[ci[k]], acc[q]);
+#pragma unroll
+  for (int q = 0; q < RPG; ++q) {
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, LPR);
+  }
+  if constexpr (LPR >= RPG) {
+    // lane q of the group stores row q: one coalesced store per wave
+    if (lane < RPG) {
+      double out = acc[0];
+#pragma unroll
+      for (int q = 1; q < RPG; ++q) out = (lane == q) ? acc[q] : out;
+      const long long row = row0 + lane;
+      if (row < n) y[row] = (bsub != nullptr) ? bsub[row] - out : out;
+    }
+  } else {
+    // fewer lanes than rows: lane l stores rows q = l, l + LPR, ...
+#pragma unroll
+    for (int q = 0; q < RPG; ++q) {
+      const long long row = row0 + q;
+      if (q % LPR == lane && row < n) y[row] = (bsub != nullptr) ? bsub[row] - acc[q] : acc[q];
+    }
+  }
 }
 
 // Dense row-major operator: one wave per row, 16-byte loads.
@@ -164,17 +227,22 @@ static hipError_t op_apply(const Op& op, const double* x, double* y, const doubl
                        bsub, gate);
     return hipGetLastError();
   }
-  const long long threads = op.n * op.lpr;
+  // lanes per row LPR (a power of two near the mean row length), rows per lane
+  // group RPG: up to 4 rows while a group is at most 8 lanes wide
+  const int lpr = op.lpr;
+  const int rpg = lpr <= 8 ? (LPR_RPG_MAX) : (lpr == 16 ? 2 : 1);
+  const long long groups = (op.n + rpg - 1) / rpg;
+  const long long threads = groups * lpr;
   unsigned grid = (unsigned)((threads + 255) / 256);
   if (grid >= 64) grid = (grid + 7) / 8 * 8;  // multiple of 8 for the XCD mapping
-  switch (op.lpr) {
-#define IGS_SPMV_CASE(L)                                                                        \
+  switch (lpr) {
+#define IGS_SPMV_CASE(L, R)                                                                     \
   case L:                                                                                       \
-    hipLaunchKernelGGL(spmv_csr_kernel<L>, dim3(grid), dim3(256), 0, s, op.n, op.row_ptr,       \
+    hipLaunchKernelGGL((spmv_csr_kernel<L, R>), dim3(grid), dim3(256), 0, s, op.n, op.row_ptr,  \
                        op.col_idx, op.vals, x, y, bsub, gate);                                  \
     break;
-    IGS_SPMV_CASE(1) IGS_SPMV_CASE(2) IGS_SPMV_CASE(4) IGS_SPMV_CASE(8) IGS_SPMV_CASE(16)
-    IGS_SPMV_CASE(32) IGS_SPMV_CASE(64)
+    IGS_SPMV_CASE(1, LPR_RPG_MAX) IGS_SPMV_CASE(2, LPR_RPG_MAX) IGS_SPMV_CASE(4, LPR_RPG_MAX)
+    IGS_SPMV_CASE(8, LPR_RPG_MAX) IGS_SPMV_CASE(16, 2) IGS_SPMV_CASE(32, 1) IGS_SPMV_CASE(64, 1)
 #undef IGS_SPMV_CASE
     default: return hipErrorInvalidValue;
   }
@@ -227,6 +295,7 @@ __global__ __launch_bounds__(256) void bnorm_kernel(const double* __restrict__ b
                                                     Work w) {
   __shared__ double red[2][256 / kWave];
   __shared__ double tot[2];
+  __shared__ double scr[256];
   double s2 = 0.0, bad = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -248,7 +317,7 @@ __global__ __launch_bounds__(256) void bnorm_kernel(const double* __restrict__ b
     for (int k = 0; k < (int)(blockDim.x / kWave); ++k) acc += red[threadIdx.x][k];
     w.part[(size_t)blockIdx.x * w.pstride + threadIdx.x] = acc;
   }
-  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2, tot)) return;
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2, tot, scr)) return;
   if (threadIdx.x == 0) {
     w.ctl->bnorm = sqrt(tot[0]);
     w.ctl->nonfinite_in = (int)tot[1];
@@ -608,6 +677,10 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
   const int nchunk = (ncol + CPW - 1) / CPW;
   const int cw = wave % wc;
   const int rw = wave / wc;
+  // rows of this wave: r0 + 64*(rw + wr*k) + lane; U row steps are loaded
+  // before any of them is used, so a wave keeps U*(CPW+2) loads in flight
+  constexpr int U = (CPW >= 16) ? 2 : ((CPW >= 4) ? 4 : 8);
+  const long long step = (long long)wr * kWave;
   if (rw < wr) {
     for (int ch = cw; ch < nchunk; ch += wc) {
       const int c0 = ch * CPW;
@@ -616,25 +689,37 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
       const double* __restrict__ vb = V + (size_t)c0 * ldv;
-      if (with_z) {
-        for (long long r = r0 + (long long)rw * kWave + lane; r < r1; r += (long long)wr * kWave) {
-          const double uu = u[r];
-          const double zz = z[r];
+      long long r = r0 + (long long)rw * kWave + lane;
+      for (; r + (U - 1) * step < r1; r += U * step) {
+        double uu[U], zz[U], vv[U][CPW];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          uu[q] = u[r + q * step];
+          zz[q] = with_z ? z[r + q * step] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) vv[q][c] = (c < nc) ? vb[(size_t)c * ldv + r + q * step] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
 #pragma unroll
           for (int c = 0; c < CPW; ++c) {
-            if (c < nc) {
-              const double v = vb[(size_t)c * ldv + r];
-              ap[c] = fma(v, uu, ap[c]);
-              aq[c] = fma(v, zz, aq[c]);
-            }
+            ap[c] = fma(vv[q][c], uu[q], ap[c]);
+            aq[c] = fma(vv[q][c], zz[q], aq[c]);
           }
         }
-      } else {
-        for (long long r = r0 + (long long)rw * kWave + lane; r < r1; r += (long long)wr * kWave) {
-          const double uu = u[r];
+      }
+      for (; r < r1; r += step) {
+        const double uu = u[r];
+        const double zz = with_z ? z[r] : 0.0;
 #pragma unroll
-          for (int c = 0; c < CPW; ++c) {
-            if (c < nc) ap[c] = fma(vb[(size_t)c * ldv + r], uu, ap[c]);
+        for (int c = 0; c < CPW; ++c) {
+          if (c < nc) {
+            const double v = vb[(size_t)c * ldv + r];
+            ap[c] = fma(v, uu, ap[c]);
+            aq[c] = fma(v, zz, aq[c]);
           }
         }
       }
@@ -652,13 +737,17 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
     }
   }
   __syncthreads();
-  double* part = w.part + (size_t)blockIdx.x * w.pstride;
-  for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) {
-    double acc = 0.0;
-    for (int k = 0; k < wr; ++k) acc += lds[(size_t)k * 2 * ncol + v];
-    part[v] = acc;
+  // the block's partial sums, written by wave 0 only (see grid_reduce_last)
+  if (wave == 0) {
+    double* part = w.part + (size_t)blockIdx.x * w.pstride;
+    for (int v = lane; v < 2 * ncol; v += kWave) {
+      double acc = 0.0;
+      for (int k = 0; k < wr; ++k) acc += lds[(size_t)k * 2 * ncol + v];
+      part[v] = acc;
+    }
   }
-  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds)) return;
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol))
+    return;
   if (raw) {
     for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) raw_out[v] = lds[v];
     return;
@@ -666,10 +755,15 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
   small_solve(w, n, j, !with_z, lds, lds + ncol, lds + 2 * ncol);
 }
 
+// Shared memory of the fused reduction: the wave partials; then the totals
+// (2 ncol) followed by either the grid-reduction scratch or the small solve.
 static size_t reduce_lds_bytes(const ReduceShape& s, int ncol) {
-  size_t a = (size_t)s.wr * 2 * ncol;
-  size_t b = (size_t)2 * ncol + 7 * (size_t)(ncol + 2);
-  return (a > b ? a : b) * sizeof(double);
+  const size_t nv = (size_t)2 * ncol;
+  size_t a = (size_t)s.wr * nv;
+  size_t b = nv + (nv > (size_t)kReduceThreads ? nv : (size_t)kReduceThreads);
+  size_t c = nv + 7 * (size_t)(ncol + 2);
+  size_t m = a > b ? a : b;
+  return (m > c ? m : c) * sizeof(double);
 }
 
 static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z,
@@ -759,7 +853,28 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     for (int k = 0; k < kUpdateRows; ++k) at[k] = ar[k] = 0.0;
     const bool full = base + (long long)(kUpdateRows - 1) * kUpdateThreads < n;
     if (full) {
-      for (int c = 0; c < j; ++c) {
+      // four columns x kUpdateRows rows of loads in flight before any FMA
+      int c = 0;
+      for (; c + 4 <= j; c += 4) {
+        double vv[4][kUpdateRows];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const double* __restrict__ vc = V + (size_t)(c + cc) * ldv + base;
+#pragma unroll
+          for (int k = 0; k < kUpdateRows; ++k) vv[cc][k] = vc[k * kUpdateThreads];
+        }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const double tc = HAS_T ? t[c + cc] : 0.0;
+          const double rc = r1[c + cc];
+#pragma unroll
+          for (int k = 0; k < kUpdateRows; ++k) {
+            if (HAS_T) at[k] = fma(vv[cc][k], tc, at[k]);
+            ar[k] = fma(vv[cc][k], rc, ar[k]);
+          }
+        }
+      }
+      for (; c < j; ++c) {
         const double* __restrict__ vc = V + (size_t)c * ldv + base;
         const double tc = HAS_T ? t[c] : 0.0;
         const double rc = r1[c];
@@ -806,6 +921,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   // norm comes from a grid reduction and finishes column j-1.
   __shared__ double red[kUpdateThreads / kWave];
   __shared__ double tot[1];
+  __shared__ double scr[kUpdateThreads];
   s2 = wave_sum(s2);
   if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s2;
   __syncthreads();
@@ -814,7 +930,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     for (int k = 0; k < kUpdateThreads / kWave; ++k) acc += red[k];
     w.part[(size_t)blockIdx.x * w.pstride] = acc;
   }
-  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 1, tot)) return;
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 1, tot, scr)) return;
   const double gamma = sqrt(tot[0]);
   // the group totals are consumed: reuse that global buffer as scratch
   double* scratch = w.gpart;
@@ -931,7 +1047,26 @@ __global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long lo
     double acc[kUpdateRows];
 #pragma unroll
     for (int k = 0; k < kUpdateRows; ++k) acc[k] = 0.0;
-    for (int c = 0; c < J; ++c) {
+    const bool full = base + (long long)(kUpdateRows - 1) * kUpdateThreads < n;
+    int c = 0;
+    if (full) {
+      for (; c + 4 <= J; c += 4) {
+        double vv[4][kUpdateRows];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const double* __restrict__ vc = w.V + (size_t)(c + cc) * w.ldv + base;
+#pragma unroll
+          for (int k = 0; k < kUpdateRows; ++k) vv[cc][k] = vc[k * kUpdateThreads];
+        }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const double yc = y[c + cc];
+#pragma unroll
+          for (int k = 0; k < kUpdateRows; ++k) acc[k] = fma(vv[cc][k], yc, acc[k]);
+        }
+      }
+    }
+    for (; c < J; ++c) {
       const double* __restrict__ vc = w.V + (size_t)c * w.ldv + base;
       const double yc = y[c];
 #pragma unroll

@@ -28,6 +28,7 @@ struct EventPair {
   int kernel;
   int j;        // iteration (-1: per cycle)
   int cycle;
+  int ran;      // -1: unknown until the cycle ends; 0/1 afterwards
   double bytes;
 };
 
@@ -79,8 +80,8 @@ struct igs_ctx {
   int V_first_valid = 0;
 
   // profiling
-  std::vector<hipEvent_t> event_pool;
-  size_t events_used = 0;
+  std::vector<hipEvent_t> event_pool;   // every event created (destroyed with the context)
+  std::vector<hipEvent_t> event_free;   // events ready for reuse
   std::vector<EventPair> pending;
   KStat stats[IGS_K_COUNT];
 
@@ -197,12 +198,15 @@ int ensure_raw(igs_ctx* c, int cols) {
 // ---- profiling ------------------------------------------------------------
 
 hipEvent_t next_event(igs_ctx* c) {
-  if (c->events_used == c->event_pool.size()) {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    c->event_pool.push_back(e);
+  if (!c->event_free.empty()) {
+    hipEvent_t e = c->event_free.back();
+    c->event_free.pop_back();
+    return e;
   }
-  return c->event_pool[c->events_used++];
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  c->event_pool.push_back(e);
+  return e;
 }
 
 struct Timed {
@@ -216,6 +220,7 @@ struct Timed {
     p.kernel = kernel;
     p.j = j;
     p.cycle = cycle;
+    p.ran = -1;
     p.bytes = bytes;
     if (p.a) (void)hipEventRecord(p.a, c->stream);
   }
@@ -237,19 +242,45 @@ bool launch_ran(int kernel, int j, int j_end, int m, bool update_at_end) {
   }
 }
 
-void harvest_cycle(igs_ctx* c, int cycle, int j_end, int m, bool update_at_end, bool xran) {
+// At the end of a cycle: record which of its launches did work.  The event
+// times themselves are read later (harvest), outside any timed loop.
+void mark_cycle(igs_ctx* c, int j_end, int m, bool update_at_end, int J, double dn) {
   for (EventPair& p : c->pending) {
-    if (p.cycle != cycle) continue;
+    if (p.ran >= 0) continue;  // launches of earlier cycles are already marked
     bool ran = launch_ran(p.kernel, p.j, j_end, m, update_at_end);
-    if (p.kernel == IGS_K_XUPDATE) ran = xran;
-    if (!ran) continue;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
-    KStat& s = c->stats[p.kernel];
-    s.launches += 1;
-    s.ms += ms;
-    s.bytes += p.bytes;
+    if (p.kernel == IGS_K_XUPDATE) {
+      ran = J > 0;
+      p.bytes = 8.0 * dn * J + 16.0 * dn;
+    }
+    p.ran = ran ? 1 : 0;
   }
+}
+
+// Read the times of every launch of finished cycles (ran >= 0) and recycle
+// their events.  Called while the GPU works on the next cycle, so the reads
+// never stall it; with wait = true (igs_profile_get) everything is drained.
+void harvest(igs_ctx* c, bool wait) {
+  if (wait) (void)hipStreamSynchronize(c->stream);
+  size_t keep = 0;
+  for (size_t k = 0; k < c->pending.size(); ++k) {
+    EventPair& p = c->pending[k];
+    if (p.ran < 0 && !wait) {
+      c->pending[keep++] = p;
+      continue;
+    }
+    if (p.ran == 1) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        KStat& s = c->stats[p.kernel];
+        s.launches += 1;
+        s.ms += ms;
+        s.bytes += p.bytes;
+      }
+    }
+    c->event_free.push_back(p.a);
+    c->event_free.push_back(p.b);
+  }
+  c->pending.resize(keep);
 }
 
 int validate_csr(igs_ctx* c, long long n, long long nnz, const int32_t* rp, const int32_t* ci,
@@ -449,8 +480,6 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   const int final_v = o.final_basis_vector ? 1 : 0;
   Work& w = c->w;
   hipStream_t s = c->stream;
-  c->events_used = 0;
-  c->pending.clear();
   c->J_first = -1;
   c->V_first_valid = 0;
 
@@ -474,6 +503,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   double relres = NAN, arn = NAN;
   bool converged = false;
   bool final_check = false;
+  int fallbacks_seen = 0;
   while (true) {
     const long long its_before = its;
     const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
@@ -508,6 +538,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       HIP_OR_FAIL(c, igs::launch_xupdate(w, n, x, s));
     }
     HIP_OR_FAIL(c, hipMemcpyAsync(c->h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (prof) harvest(c, false);  // earlier cycles, while this one runs
     HIP_OR_FAIL(c, hipStreamSynchronize(s));
     const Ctl h = *c->h_ctl;
     status = h.status;
@@ -515,13 +546,11 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     if (prof) {
       int j_end = J;
       if (status == igs::kNonfinite) j_end = J + 1;
-      const bool upd_end = (h.mode_iter == j_end) && (h.mode == igs::kUpdVOnly ||
-                                                      status == igs::kLagnorm);
-      // x-update bytes depend on J, known only now
-      for (EventPair& p : c->pending)
-        if (p.cycle == cycles && p.kernel == IGS_K_XUPDATE) p.bytes = 8.0 * dn * J + 16.0 * dn;
-      harvest_cycle(c, cycles, j_end, m, upd_end, J > 0);
+      const bool fell_back = h.fallbacks > fallbacks_seen;
+      const bool upd_end = (h.mode_iter == j_end) && (h.mode == igs::kUpdVOnly || fell_back);
+      mark_cycle(c, j_end, m, upd_end, final_check ? 0 : J, dn);
     }
+    fallbacks_seen = h.fallbacks;
     if (cycles == 0 && !final_check) {
       c->J_first = J;
       c->ldh_first = w.ldh;
@@ -664,6 +693,7 @@ extern "C" int igs_kernel_update(igs_ctx* c, double* V, int64_t ldv, int j, cons
 extern "C" int igs_profile_get(igs_ctx* c, int which, int64_t* launches, double* total_ms,
                                double* total_bytes) {
   if (!c || which < 0 || which >= IGS_K_COUNT) return IGS_EINVAL;
+  harvest(c, true);
   if (launches) *launches = c->stats[which].launches;
   if (total_ms) *total_ms = c->stats[which].ms;
   if (total_bytes) *total_bytes = c->stats[which].bytes;
@@ -672,6 +702,7 @@ extern "C" int igs_profile_get(igs_ctx* c, int which, int64_t* launches, double*
 
 extern "C" int igs_profile_reset(igs_ctx* c) {
   if (!c) return IGS_EINVAL;
+  harvest(c, true);
   for (KStat& s : c->stats) s = KStat{};
   return IGS_OK;
 }

@@ -39,6 +39,8 @@ CSR_CASES = {
     "convdiff3d_17": lambda: W.convdiff3d(17, 50.0),
     "convdiff2d_31": lambda: W.convdiff2d(31, 10.0),
     "random_short_rows_empty": lambda: _random_csr(3001, 3.0, 1, empty_rows=(0, 17, 3000)),
+    "random_two_lanes": lambda: _random_csr(2049, 1.6, 5, empty_rows=(5,)),
+    "diagonal_one_lane": lambda: W.csr_from_dense(np.diag(np.arange(1.0, 40.0))),
     "random_long_rows": lambda: _random_csr(1500, 40.0, 2),
     "single_row": lambda: W.csr_from_dense(np.array([[2.5]])),
 }
