@@ -131,42 +131,51 @@ def main():
     s = Solver(a)
     b_d = torch.as_tensor(b, device=dev)
     x_d = torch.zeros_like(b_d)
-    opts = {} if args.no_profile else {"profile": 1}
 
-    def solve(gs):
+    def solve(gs, profile_kernels=None):
         x_d.zero_()
+        o = {}
+        if profile_kernels is not None and not args.no_profile:
+            o = {"profile": 1, "profile_kernels": profile_kernels}
         with torch.cuda.stream(s.stream):
-            return igs.igs_solve_opts(s.ctx, b_d, x_d, args.restart, args.tol, gs,
-                                      igs.IgsOpts(**opts))
+            return igs.igs_solve_opts(s.ctx, b_d, x_d, args.restart, args.tol, gs, igs.IgsOpts(**o))
 
+    def kernel_table(prof):
+        out = {}
+        for name, (launches, ms, by) in prof.items():
+            if launches:
+                out[name] = {"launches": launches, "ms": ms, "avg_us": 1e3 * ms / launches,
+                             "GBs": by / (ms * 1e6) if ms > 0 else None, "bytes": by}
+        return out
+
+    # warmup: every kernel timed, to find the dominant one
     for _ in range(args.warmup):
-        rc, info = solve(2)
+        rc, info = solve(2, profile_kernels=0)
         log(f"[bench] warmup: rc={rc} iters={info['iters']} relres={info['relres_true']:.2e}")
+    warm = kernel_table(s.profile()) if not args.no_profile else {}
+    dominant = max(("spmv", "reduce", "update"), key=lambda k: warm.get(k, {}).get("ms", 0.0))
+    dom_mask = 1 << igs.KERNEL_NAMES.index(dominant)
     s.profile_reset()
     torch.cuda.synchronize()
+    # timed region: HIP events around every launch of the dominant kernel only
     iters = 0
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        rc, info = solve(2)
+        rc, info = solve(2, profile_kernels=dom_mask)
         iters += info["iters"]
         if rc != 0:
             raise RuntimeError(f"solve did not converge: {info}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    prof = s.profile()
+    kern = kernel_table(s.profile()) if not args.no_profile else {}
     log(f"[bench] timed {args.steps} solves: {elapsed:.3f}s, {iters} iterations")
 
     beta, anorm_est = backward_error_torch(torch, a, b_d, x_d)
     info2 = info
-
-    # per-kernel figures from the HIP events of the timed region
-    kern = {}
-    for name, (launches, ms, by) in prof.items():
-        if launches:
-            kern[name] = {"launches": launches, "ms": ms, "avg_us": 1e3 * ms / launches,
-                          "GBs": by / (ms * 1e6) if ms > 0 else None, "bytes": by}
-    total_bytes = sum(k["bytes"] for k in kern.values())
-    dominant = max(("spmv", "reduce", "update"), key=lambda k: kern.get(k, {}).get("ms", 0.0))
+    # algorithmic bytes of the whole solve from the all-kernel warmup profile
+    warm_bytes = sum(k["bytes"] for k in warm.values())
+    warm_iters = info["iters"] * max(args.warmup, 1)
+    total_bytes = warm_bytes / warm_iters * iters if warm_iters else 0.0
     dk = kern.get(dominant, {})
     achieved = dk.get("GBs")
     traffic = measured_traffic(dominant, workload)
@@ -210,8 +219,9 @@ def main():
         "backward_error": beta,
         "anorm2_estimate": anorm_est,
         "relres_true": info2["relres_true"],
-        "kernels": {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
-                        "GBs": round(v["GBs"], 1) if v["GBs"] else None} for k, v in kern.items()},
+        "kernels_warmup": {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
+                               "GBs": round(v["GBs"], 1) if v["GBs"] else None}
+                           for k, v in warm.items()},
         "roofline": roofline,
         "gs1": {"iters": info1["iters"], "seconds": dt1, "iters_per_s": info1["iters"] / dt1,
                 "converged": bool(info1["converged"])},

@@ -79,7 +79,9 @@ typedef struct igs_opts {
   int max_cycles;       /* > 0: stop after this many restart cycles            */
   int keep_first_basis; /* 1: keep a device copy of the first cycle's V for
                            igs_debug_copy_V (costs one copy of the basis)      */
-  int reserved[6];
+  int profile_kernels;  /* with profile = 1: bit (1 << IGS_K_*) selects the
+                           kernels to time; 0 means all                        */
+  int reserved[5];
 } igs_opts;
 
 /* Result summary of a solve.  Any pointer argument of this type may be NULL. */

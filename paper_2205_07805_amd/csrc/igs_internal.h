@@ -74,8 +74,9 @@ struct Op {
 struct Work {
   double* V; long long ldv;      // basis, column-major, m+1 columns
   double* z;                     // A u of the current iteration
-  double* H; double* R;          // Hessenberg (unrotated / rotated), column-major, ld = ldh
-  double* T;                     // (I + L)^{-1}, row-major, ld = ldt
+  double* H;                     // Hessenberg before rotation, packed by columns (m(m+3)/2)
+  double* R;                     // rotated Hessenberg, column-major, ld = ldh
+  double* T;                     // (I + L)^{-1}, packed lower triangle by rows ((m+1)(m+2)/2)
   double* L;                     // strictly lower L, column-major, ld = ldt
   int ldh; int ldt;
   double* cs; double* sn; double* g; double* y;

@@ -32,6 +32,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Two consecutive rows of a column as one 16-byte access.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+// Streaming read of data used once per kernel (the basis V): non-temporal,
+// so it does not displace reused data from the caches.
+__device__ __forceinline__ dvec2 ld_stream2(const double* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+}
+__device__ __forceinline__ dvec2 ld2(const double* p) { return *reinterpret_cast<const dvec2*>(p); }
+
 __device__ __forceinline__ int load_agent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -366,10 +376,47 @@ __device__ double givens_column(const Work& w, int c, double* col, const double*
   return fabs(sn * gc);
 }
 
+// Packed storage of the small matrices (device memory):
+//   T = (I + L)^{-1}, lower triangular: row i holds T[i, 0..i] at tri_row(i);
+//   H, upper Hessenberg:               column c holds H[0..c+1, c] at hess_col(c).
+// Both grow by appending (a row of T, a column of H per iteration), so the
+// part an iteration reads is one contiguous prefix.
+__device__ __forceinline__ size_t tri_row(int i) { return (size_t)i * (i + 1) / 2; }
+__device__ __forceinline__ size_t hess_col(int c) { return (size_t)c * (c + 3) / 2; }
+
+// Copy count doubles from global src to shared dst with every thread's loads
+// issued in batches of eight (about one memory latency for the whole copy).
+__device__ void stage_copy(double* dst, const double* src, size_t count) {
+  const size_t nt = blockDim.x;
+  for (size_t k0 = threadIdx.x; k0 < count; k0 += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const size_t k = k0 + q * nt;
+      v[q] = (k < count) ? src[k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const size_t k = k0 + q * nt;
+      if (k < count) dst[k] = v[q];
+    }
+  }
+}
+
+// Largest staged prefix of T and H (doubles of shared memory in the last
+// block of the reduction); larger iterations read them from global memory.
+constexpr size_t kStageMax = 6144;
+__host__ __device__ __forceinline__ size_t stage_count(int j) {
+  if (j < 1) return 0;
+  const size_t c = (size_t)j * (j + 1) / 2 + (size_t)(j - 1) * (j + 2) / 2;
+  return c <= kStageMax ? c : 0;
+}
+
 // Finish Hessenberg column j-1 with subdiagonal gamma: store H and the rotated
-// column, apply the rotation, and run the breakdown test.  hcol (shared) holds
-// H[0:j, j-1]; scratch needs 2*j doubles.  Called by all threads of a block.
-// Returns 1 on breakdown, 0 otherwise; ctl->gabs is updated.
+// column, apply the rotation, and run the breakdown test.  hcol (shared or
+// global) holds H[0:j, j-1]; scratch needs 2*j doubles.  Called by all
+// threads of a block.  Returns 1 on breakdown, 0 otherwise; ctl->gabs is
+// updated.
 __device__ int finish_column(const Work& w, int j, double* hcol, double gamma, double* scratch,
                              long long n) {
   __shared__ double s_hn;
@@ -377,14 +424,15 @@ __device__ int finish_column(const Work& w, int j, double* hcol, double gamma, d
   double* scs = scratch;
   double* ssn = scratch + j;
   const int c = j - 1;
+  double* hc = w.H + hess_col(c);
   for (int i = threadIdx.x; i < j; i += blockDim.x) {
-    w.H[(size_t)c * w.ldh + i] = hcol[i];
+    hc[i] = hcol[i];
     if (i < c) {
       scs[i] = w.cs[i];
       ssn[i] = w.sn[i];
     }
   }
-  if (threadIdx.x == 0) w.H[(size_t)c * w.ldh + j] = gamma;
+  if (threadIdx.x == 0) hc[j] = gamma;
   __syncthreads();
   if (threadIdx.x < kWave) {
     const double hn2 = wave_dot(hcol, hcol, j);
@@ -408,6 +456,7 @@ __device__ int finish_column(const Work& w, int j, double* hcol, double gamma, d
 // ---------------------------------------------------------------------------
 // The small solve of iteration j, run by the last block of the reduction.
 // P[c] = V_c^T u, Q[c] = V_c^T z for c <= j (P[j] = u^T u, Q[j] = u^T z).
+// sm: shared scratch of 7 (j + 2) doubles, followed by stage_count(j) more.
 // ---------------------------------------------------------------------------
 
 __device__ void small_solve(const Work& w, long long n, int j, bool tail, const double* P,
@@ -417,7 +466,6 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
   const int wave = tid / kWave;
   const int lane = tid % kWave;
   const int nw = blockDim.x / kWave;
-  const int ldt = w.ldt;
   // shared scratch, each of length j + 2
   const int L1 = j + 2;
   double* st = sm;            // t (second sweep coefficients)
@@ -466,10 +514,24 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     return;
   }
 
+  // ---- T rows 0..j-1 and H columns 0..j-2 (staged in shared memory if small)
+  const double* Ts = w.T;
+  const double* Hs = w.H;
+  const size_t nstage = stage_count(j);
+  if (nstage) {
+    double* stg = sm + 7 * L1;
+    const size_t nT = tri_row(j);
+    stage_copy(stg, w.T, nT);
+    stage_copy(stg + nT, w.H, nstage - nT);
+    __syncthreads();
+    Ts = stg;
+    Hs = stg + nT;
+  }
+
   // ---- second sweep t = (I + L_{0:j,0:j})^{-1} p = T_j p  (gs = 2) ----------
   if (gs == 2) {
     for (int i = wave; i < j; i += nw) {
-      const double* trow = w.T + (size_t)i * ldt;
+      const double* trow = Ts + tri_row(i);
       double acc = 0.0;
       for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], P[c], acc);
       acc = wave_sum(acc);
@@ -482,21 +544,22 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     const double pp = wave_dot(P, P, j);
     if (lane == 0) s_pp = pp;
   }
+  {
+    const double igp = 1.0 / ctl->gamma_prev;
+    for (int i = tid; i < j; i += blockDim.x) {
+      shc[i] = w.coef_r1[i];                       // r1 of the previous iteration
+      if (i < j - 1) sx[i] = w.coef_t[i] * igp;    // t_prev / gamma_prev
+    }
+  }
   __syncthreads();
 
   // ---- finished column j-1:  r1_prev + t - H[0:j, 0:j-1] (t_prev / gamma_prev)
-  {
-    const double igp = 1.0 / ctl->gamma_prev;
-    for (int i = tid; i < j - 1; i += blockDim.x) sx[i] = w.coef_t[i] * igp;
-    __syncthreads();
-    for (int i = tid; i < j; i += blockDim.x) {
-      double acc = 0.0;
-      if (gs == 2) {
-        for (int c = (i > 0 ? i - 1 : 0); c < j - 1; ++c)
-          acc = fma(w.H[(size_t)c * w.ldh + i], sx[c], acc);
-      }
-      shc[i] = w.coef_r1[i] + st[i] - acc;
+  for (int i = tid; i < j; i += blockDim.x) {
+    double acc = 0.0;
+    if (gs == 2) {
+      for (int c = (i > 0 ? i - 1 : 0); c < j - 1; ++c) acc = fma(Hs[hess_col(c) + i], sx[c], acc);
     }
+    shc[i] = shc[i] + st[i] - acc;
   }
   __syncthreads();
 
@@ -518,8 +581,9 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
   if (s_flag) {
     // Cancellation in u^T u - p^T p: store the column without its subdiagonal
     // and let the update kernel form w = u - V t and its explicit norm.
+    double* hc = w.H + hess_col(j - 1);
     for (int i = tid; i < j; i += blockDim.x) {
-      w.H[(size_t)(j - 1) * w.ldh + i] = shc[i];
+      hc[i] = shc[i];
       w.coef_t[i] = st[i];
     }
     if (tid == 0) {
@@ -547,15 +611,18 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
   for (int c = tid; c < j; c += blockDim.x) {
     const double l = P[c] * ig;
     sl[c] = l;
-    w.L[(size_t)c * ldt + j] = l;
+    w.L[(size_t)c * w.ldt + j] = l;
   }
   __syncthreads();
-  for (int c = tid; c < j; c += blockDim.x) {
-    double acc = 0.0;
-    for (int i = c; i < j; ++i) acc = fma(sl[i], w.T[(size_t)i * ldt + c], acc);
-    w.T[(size_t)j * ldt + c] = -acc;
+  {
+    double* trow = w.T + tri_row(j);
+    for (int c = tid; c < j; c += blockDim.x) {
+      double acc = 0.0;
+      for (int i = c; i < j; ++i) acc = fma(sl[i], Ts[tri_row(i) + c], acc);
+      trow[c] = -acc;
+    }
+    if (tid == 0) trow[j] = 1.0;
   }
-  if (tid == 0) w.T[(size_t)j * ldt + j] = 1.0;
 
   // ---- stopping tests ----------------------------------------------------------
   if (tid == 0) {
@@ -596,7 +663,7 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     for (int c = tid; c < j; c += blockDim.x) sx[c] = Q[c] * ig;
     __syncthreads();
     for (int i = wave; i < j; i += nw) {
-      const double* trow = w.T + (size_t)i * ldt;
+      const double* trow = Ts + tri_row(i);
       double acc = 0.0;
       for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], sx[c], acc);
       acc = wave_sum(acc);
@@ -648,7 +715,7 @@ static ReduceShape reduce_shape(long long n, int ncol) {
   if (nb > 512) nb = 512;
   if (nb < 1) nb = 1;
   long long rpb = (n + nb - 1) / nb;
-  rpb = (rpb + 63) / 64 * 64;
+  rpb = (rpb + 127) / 128 * 128;  // even row pairs per block
   nb = (n + rpb - 1) / rpb;
   s.nblocks = (int)nb;
   s.rows_per_block = rpb;
@@ -657,7 +724,7 @@ static ReduceShape reduce_shape(long long n, int ncol) {
 
 int reduce_grid(long long n) { return reduce_shape(n, 1).nblocks; }
 
-template <int CPW>
+template <int CPW, bool VEC>
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
     Work w, long long n, int j, int with_z, long long rows_per_block, int wc, int wr,
     const double* __restrict__ Vraw, long long ldv_raw, const double* __restrict__ zraw,
@@ -677,10 +744,6 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
   const int nchunk = (ncol + CPW - 1) / CPW;
   const int cw = wave % wc;
   const int rw = wave / wc;
-  // rows of this wave: r0 + 64*(rw + wr*k) + lane; U row steps are loaded
-  // before any of them is used, so a wave keeps U*(CPW+2) loads in flight
-  constexpr int U = (CPW >= 16) ? 2 : ((CPW >= 4) ? 4 : 8);
-  const long long step = (long long)wr * kWave;
   if (rw < wr) {
     for (int ch = cw; ch < nchunk; ch += wc) {
       const int c0 = ch * CPW;
@@ -689,37 +752,89 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
       const double* __restrict__ vb = V + (size_t)c0 * ldv;
-      long long r = r0 + (long long)rw * kWave + lane;
-      for (; r + (U - 1) * step < r1; r += U * step) {
-        double uu[U], zz[U], vv[U][CPW];
+      long long r;
+      if constexpr (VEC) {
+        // lane owns rows (r, r+1): 16-byte non-temporal loads of V; U row
+        // steps are loaded before any is used (U*(CPW+2) loads in flight)
+        constexpr int U = (CPW >= 16) ? 1 : ((CPW >= 8) ? 2 : 4);
+        const long long step = 2LL * wr * kWave;
+        r = r0 + 2LL * ((long long)rw * kWave + lane);
+        for (; r + (U - 1) * step + 1 < r1; r += U * step) {
+          dvec2 uu[U], zz[U], vv[U][CPW];
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-          uu[q] = u[r + q * step];
-          zz[q] = with_z ? z[r + q * step] : 0.0;
-        }
+          for (int q = 0; q < U; ++q) {
+            uu[q] = ld2(u + r + q * step);
+            zz[q] = with_z ? ld2(z + r + q * step) : dvec2{0.0, 0.0};
+          }
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
+          for (int q = 0; q < U; ++q) {
 #pragma unroll
-          for (int c = 0; c < CPW; ++c) vv[q][c] = (c < nc) ? vb[(size_t)c * ldv + r + q * step] : 0.0;
-        }
+            for (int c = 0; c < CPW; ++c)
+              vv[q][c] = (c < nc) ? ld_stream2(vb + (size_t)c * ldv + r + q * step) : dvec2{0.0, 0.0};
+          }
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
+          for (int q = 0; q < U; ++q) {
 #pragma unroll
-          for (int c = 0; c < CPW; ++c) {
-            ap[c] = fma(vv[q][c], uu[q], ap[c]);
-            aq[c] = fma(vv[q][c], zz[q], aq[c]);
+            for (int c = 0; c < CPW; ++c) {
+              ap[c] = fma(vv[q][c].x, uu[q].x, ap[c]);
+              ap[c] = fma(vv[q][c].y, uu[q].y, ap[c]);
+              aq[c] = fma(vv[q][c].x, zz[q].x, aq[c]);
+              aq[c] = fma(vv[q][c].y, zz[q].y, aq[c]);
+            }
           }
         }
-      }
-      for (; r < r1; r += step) {
-        const double uu = u[r];
-        const double zz = with_z ? z[r] : 0.0;
+        // remaining rows one at a time (ragged end of the block's range)
+        for (long long rr = r; rr < r1; rr += step) {
+          for (long long r2 = rr; r2 < rr + 2 && r2 < r1; ++r2) {
+            const double uu = u[r2];
+            const double zz = with_z ? z[r2] : 0.0;
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          if (c < nc) {
-            const double v = vb[(size_t)c * ldv + r];
-            ap[c] = fma(v, uu, ap[c]);
-            aq[c] = fma(v, zz, aq[c]);
+            for (int c = 0; c < CPW; ++c) {
+              if (c < nc) {
+                const double v = vb[(size_t)c * ldv + r2];
+                ap[c] = fma(v, uu, ap[c]);
+                aq[c] = fma(v, zz, aq[c]);
+              }
+            }
+          }
+        }
+      } else {
+        // any alignment: 8-byte loads, U row steps batched
+        constexpr int U = (CPW >= 16) ? 2 : ((CPW >= 4) ? 4 : 8);
+        const long long step = (long long)wr * kWave;
+        r = r0 + (long long)rw * kWave + lane;
+        for (; r + (U - 1) * step < r1; r += U * step) {
+          double uu[U], zz[U], vv[U][CPW];
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            uu[q] = u[r + q * step];
+            zz[q] = with_z ? z[r + q * step] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+              vv[q][c] = (c < nc) ? vb[(size_t)c * ldv + r + q * step] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              ap[c] = fma(vv[q][c], uu[q], ap[c]);
+              aq[c] = fma(vv[q][c], zz[q], aq[c]);
+            }
+          }
+        }
+        for (; r < r1; r += step) {
+          const double uu = u[r];
+          const double zz = with_z ? z[r] : 0.0;
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            if (c < nc) {
+              const double v = vb[(size_t)c * ldv + r];
+              ap[c] = fma(v, uu, ap[c]);
+              aq[c] = fma(v, zz, aq[c]);
+            }
           }
         }
       }
@@ -761,7 +876,7 @@ static size_t reduce_lds_bytes(const ReduceShape& s, int ncol) {
   const size_t nv = (size_t)2 * ncol;
   size_t a = (size_t)s.wr * nv;
   size_t b = nv + (nv > (size_t)kReduceThreads ? nv : (size_t)kReduceThreads);
-  size_t c = nv + 7 * (size_t)(ncol + 2);
+  size_t c = nv + 7 * (size_t)(ncol + 2) + stage_count(ncol - 1);
   size_t m = a > b ? a : b;
   return (m > c ? m : c) * sizeof(double);
 }
@@ -773,14 +888,21 @@ static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z
   const ReduceShape sh = reduce_shape(n, ncol);
   const size_t lds = reduce_lds_bytes(sh, ncol);
   if (nblocks_out) *nblocks_out = sh.nblocks;
-  switch (sh.cpw) {
-#define IGS_RED_CASE(C)                                                                        \
-  case C:                                                                                      \
-    hipLaunchKernelGGL(reduce_kernel<C>, dim3(sh.nblocks), dim3(kReduceThreads), lds, s, w, n, \
-                       j, with_z ? 1 : 0, sh.rows_per_block, sh.wc, sh.wr, Vraw, ldv_raw, zraw, \
-                       raw_out);                                                               \
+  // 16-byte row pairs need an even leading dimension and aligned columns
+  const double* Vp = raw_out ? Vraw : w.V;
+  const double* zp = raw_out ? zraw : w.z;
+  const long long ldv = raw_out ? ldv_raw : w.ldv;
+  const bool vec = (ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(zp) % 16 == 0);
+  switch (sh.cpw * 2 + (vec ? 1 : 0)) {
+#define IGS_RED_CASE(C, VV)                                                                    \
+  case C * 2 + VV:                                                                             \
+    hipLaunchKernelGGL((reduce_kernel<C, VV>), dim3(sh.nblocks), dim3(kReduceThreads), lds, s, \
+                       w, n, j, with_z ? 1 : 0, sh.rows_per_block, sh.wc, sh.wr, Vraw, ldv_raw, \
+                       zraw, raw_out);                                                         \
     break;
-    IGS_RED_CASE(1) IGS_RED_CASE(2) IGS_RED_CASE(4) IGS_RED_CASE(8) IGS_RED_CASE(16)
+    IGS_RED_CASE(1, 0) IGS_RED_CASE(2, 0) IGS_RED_CASE(4, 0) IGS_RED_CASE(8, 0) IGS_RED_CASE(16, 0)
+    IGS_RED_CASE(1, 1) IGS_RED_CASE(2, 1) IGS_RED_CASE(4, 1) IGS_RED_CASE(8, 1) IGS_RED_CASE(16, 1)
 #undef IGS_RED_CASE
     default: return hipErrorInvalidValue;
   }
@@ -807,7 +929,7 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
 // Basis update: one pass over V_{0:j}
 // ---------------------------------------------------------------------------
 
-template <bool HAS_T>
+template <bool HAS_T, bool VEC>
 __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     Work w, long long n, int j, double* __restrict__ Vraw, long long ldv_raw,
     const double* __restrict__ zraw, const double* __restrict__ traw,
@@ -847,6 +969,75 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   const long long ntiles = (n + kTile - 1) / kTile;
   double s2 = 0.0;  // ||w||^2 partial (fallback only)
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    if constexpr (VEC) {
+      // Full tile: thread owns the row pairs p0 = 2t and p1 = 2t + 2*kUpdateThreads
+      // of the tile; V is streamed with 16-byte non-temporal loads.
+      const long long tb = tile * kTile;
+      if (tb + kTile <= n) {
+        const long long p0 = tb + 2LL * threadIdx.x;
+        const long long p1 = p0 + 2LL * kUpdateThreads;
+        dvec2 a0 = {0.0, 0.0}, a1 = {0.0, 0.0}, b0 = {0.0, 0.0}, b1 = {0.0, 0.0};
+        int c = 0;
+        for (; c + 4 <= j; c += 4) {
+          dvec2 v0[4], v1[4];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const double* vc = V + (size_t)(c + cc) * ldv;
+            v0[cc] = ld_stream2(vc + p0);
+            v1[cc] = ld_stream2(vc + p1);
+          }
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const double tc = HAS_T ? t[c + cc] : 0.0;
+            const double rc = r1[c + cc];
+            if (HAS_T) {
+              a0.x = fma(v0[cc].x, tc, a0.x); a0.y = fma(v0[cc].y, tc, a0.y);
+              a1.x = fma(v1[cc].x, tc, a1.x); a1.y = fma(v1[cc].y, tc, a1.y);
+            }
+            b0.x = fma(v0[cc].x, rc, b0.x); b0.y = fma(v0[cc].y, rc, b0.y);
+            b1.x = fma(v1[cc].x, rc, b1.x); b1.y = fma(v1[cc].y, rc, b1.y);
+          }
+        }
+        for (; c < j; ++c) {
+          const double* vc = V + (size_t)c * ldv;
+          const dvec2 v0 = ld_stream2(vc + p0);
+          const dvec2 v1 = ld_stream2(vc + p1);
+          const double tc = HAS_T ? t[c] : 0.0;
+          const double rc = r1[c];
+          if (HAS_T) {
+            a0.x = fma(v0.x, tc, a0.x); a0.y = fma(v0.y, tc, a0.y);
+            a1.x = fma(v1.x, tc, a1.x); a1.y = fma(v1.y, tc, a1.y);
+          }
+          b0.x = fma(v0.x, rc, b0.x); b0.y = fma(v0.y, rc, b0.y);
+          b1.x = fma(v1.x, rc, b1.x); b1.y = fma(v1.y, rc, b1.y);
+        }
+        const dvec2 u0 = ld2(vj + p0);
+        const dvec2 u1 = ld2(vj + p1);
+        if (fallback) {
+          const dvec2 w0 = u0 - a0;
+          const dvec2 w1 = u1 - a1;
+          *reinterpret_cast<dvec2*>(vj + p0) = w0;
+          *reinterpret_cast<dvec2*>(vj + p1) = w1;
+          s2 = fma(w0.x, w0.x, s2); s2 = fma(w0.y, w0.y, s2);
+          s2 = fma(w1.x, w1.x, s2); s2 = fma(w1.y, w1.y, s2);
+        } else {
+          const dvec2 n0 = (u0 - a0) * ig;
+          const dvec2 n1 = (u1 - a1) * ig;
+          *reinterpret_cast<dvec2*>(vj + p0) = n0;
+          *reinterpret_cast<dvec2*>(vj + p1) = n1;
+          if (need_r) {
+            const dvec2 z0 = ld2(z + p0);
+            const dvec2 z1 = ld2(z + p1);
+            dvec2 o0, o1;
+            o0.x = z0.x * ig - b0.x - n0.x * rj; o0.y = z0.y * ig - b0.y - n0.y * rj;
+            o1.x = z1.x * ig - b1.x - n1.x * rj; o1.y = z1.y * ig - b1.y - n1.y * rj;
+            *reinterpret_cast<dvec2*>(un + p0) = o0;
+            *reinterpret_cast<dvec2*>(un + p1) = o1;
+          }
+        }
+        continue;
+      }
+    }
     const long long base = tile * kTile + threadIdx.x;
     double at[kUpdateRows], ar[kUpdateRows];
 #pragma unroll
@@ -935,7 +1126,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   // the group totals are consumed: reuse that global buffer as scratch
   double* scratch = w.gpart;
   double* hcol = scratch;
-  for (int i = threadIdx.x; i < j; i += blockDim.x) hcol[i] = w.H[(size_t)(j - 1) * w.ldh + i];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) hcol[i] = w.H[hess_col(j - 1) + i];
   __syncthreads();
   const int brk = finish_column(w, j, hcol, gamma, scratch + (j + 2), n);
   if (threadIdx.x == 0) {
@@ -964,13 +1155,25 @@ static unsigned update_grid(long long n) {
 
 hipError_t launch_update(const Work& w, long long n, int j, int gs, hipStream_t s) {
   // With one Gauss-Seidel sweep there is no second-sweep vector t, and the
-  // kernel variant without it skips one FMA stream.
+  // kernel variant without it skips one FMA stream.  16-byte accesses need
+  // an even leading dimension and 16-byte aligned columns.
+  const bool vec = (w.ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(w.V) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(w.z) % 16 == 0);
+  const dim3 g(update_grid(n)), b(kUpdateThreads);
   if (gs == 2) {
-    hipLaunchKernelGGL(update_kernel<true>, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w,
-                       n, j, nullptr, 0LL, nullptr, nullptr, nullptr, 0.0, 0);
+    if (vec)
+      hipLaunchKernelGGL((update_kernel<true, true>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
+                         nullptr, nullptr, 0.0, 0);
+    else
+      hipLaunchKernelGGL((update_kernel<true, false>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
+                         nullptr, nullptr, 0.0, 0);
   } else {
-    hipLaunchKernelGGL(update_kernel<false>, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w,
-                       n, j, nullptr, 0LL, nullptr, nullptr, nullptr, 0.0, 0);
+    if (vec)
+      hipLaunchKernelGGL((update_kernel<false, true>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
+                         nullptr, nullptr, 0.0, 0);
+    else
+      hipLaunchKernelGGL((update_kernel<false, false>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
+                         nullptr, nullptr, 0.0, 0);
   }
   return hipGetLastError();
 }
@@ -978,8 +1181,14 @@ hipError_t launch_update(const Work& w, long long n, int j, int gs, hipStream_t 
 hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
                              const double* t, const double* r1, double inv_gamma, hipStream_t s) {
   Work w{};
-  hipLaunchKernelGGL(update_kernel<true>, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w, n,
-                     j, V, ldv, z, t, r1, inv_gamma, 1);
+  const bool vec = (ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(V) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(z) % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((update_kernel<true, true>), dim3(update_grid(n)), dim3(kUpdateThreads), 0,
+                       s, w, n, j, V, ldv, z, t, r1, inv_gamma, 1);
+  else
+    hipLaunchKernelGGL((update_kernel<true, false>), dim3(update_grid(n)), dim3(kUpdateThreads), 0,
+                       s, w, n, j, V, ldv, z, t, r1, inv_gamma, 1);
   return hipGetLastError();
 }
 

@@ -150,9 +150,9 @@ int ensure_workspace(igs_ctx* c, int m) {
   if (w.pstride < 8) w.pstride = 8;
   HIP_OR_FAIL(c, dalloc(&w.V, (size_t)w.ldv * (m + 1)));
   HIP_OR_FAIL(c, dalloc(&w.z, (size_t)w.ldv));
-  HIP_OR_FAIL(c, dalloc(&w.H, (size_t)w.ldh * m));
+  HIP_OR_FAIL(c, dalloc(&w.H, (size_t)m * (m + 3) / 2));
   HIP_OR_FAIL(c, dalloc(&w.R, (size_t)w.ldh * m));
-  HIP_OR_FAIL(c, dalloc(&w.T, (size_t)w.ldt * w.ldt));
+  HIP_OR_FAIL(c, dalloc(&w.T, (size_t)(m + 1) * (m + 2) / 2));
   HIP_OR_FAIL(c, dalloc(&w.L, (size_t)w.ldt * w.ldt));
   HIP_OR_FAIL(c, dalloc(&w.cs, (size_t)m));
   HIP_OR_FAIL(c, dalloc(&w.sn, (size_t)m));
@@ -169,9 +169,9 @@ int ensure_workspace(igs_ctx* c, int m) {
   // Zero-fill at allocation, outside any captured work.
   HIP_OR_FAIL(c, hipMemsetAsync(w.tickets, 0, sizeof(unsigned) * (igs::kMaxGroups + 1), c->stream));
   HIP_OR_FAIL(c, hipMemsetAsync(w.ctl, 0, sizeof(Ctl), c->stream));
-  HIP_OR_FAIL(c, hipMemsetAsync(w.T, 0, sizeof(double) * w.ldt * w.ldt, c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(w.T, 0, sizeof(double) * (m + 1) * (m + 2) / 2, c->stream));
   HIP_OR_FAIL(c, hipMemsetAsync(w.L, 0, sizeof(double) * w.ldt * w.ldt, c->stream));
-  HIP_OR_FAIL(c, hipMemsetAsync(w.H, 0, sizeof(double) * w.ldh * m, c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(w.H, 0, sizeof(double) * m * (m + 3) / 2, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   memset(c->h_ctl, 0, sizeof(Ctl));
   c->m_alloc = m;
@@ -213,7 +213,8 @@ struct Timed {
   igs_ctx* c;
   bool on;
   EventPair p{};
-  Timed(igs_ctx* c_, bool on_, int kernel, int j, int cycle, double bytes) : c(c_), on(on_) {
+  Timed(igs_ctx* c_, int mask, int kernel, int j, int cycle, double bytes)
+      : c(c_), on((mask >> kernel) & 1) {
     if (!on) return;
     p.a = next_event(c);
     p.b = next_event(c);
@@ -477,6 +478,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   const long long maxit = o.maxit > 0 ? o.maxit : 20 * n;
   const double tau = o.lagnorm_tau > 0.0 ? o.lagnorm_tau : 1e-4;
   const bool prof = o.profile != 0;
+  const int pmask = prof ? (o.profile_kernels ? o.profile_kernels : (1 << IGS_K_COUNT) - 1) : 0;
   const int final_v = o.final_basis_vector ? 1 : 0;
   Work& w = c->w;
   hipStream_t s = c->stream;
@@ -508,7 +510,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     const long long its_before = its;
     const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
     {
-      Timed tm(c, prof, IGS_K_RESIDUAL, -1, cycles, op_bytes + 8.0 * dn);
+      Timed tm(c, pmask, IGS_K_RESIDUAL, -1, cycles, op_bytes + 8.0 * dn);
       HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w.V, w, its_before, maxit_cycle, m,
                                           gs_iters, final_v, tol, tau, s));
     }
@@ -516,11 +518,11 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     for (int j = 0; j <= jmax; ++j) {
       const double* u = w.V + (size_t)j * w.ldv;
       if (j < m) {
-        Timed tm(c, prof, IGS_K_SPMV, j, cycles, op_bytes);
+        Timed tm(c, pmask, IGS_K_SPMV, j, cycles, op_bytes);
         HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, w.z, w.ctl, s));
       }
       {
-        Timed tm(c, prof, IGS_K_REDUCE, j, cycles, 8.0 * dn * (j + 1) + (j < m ? 8.0 * dn : 0.0));
+        Timed tm(c, pmask, IGS_K_REDUCE, j, cycles, 8.0 * dn * (j + 1) + (j < m ? 8.0 * dn : 0.0));
         HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, s, nullptr));
       }
       if (final_check) break;
@@ -528,13 +530,13 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       // when the lagged norm cancelled there, or writes v_m on request, and
       // returns at once otherwise.  It never writes column m + 1.
       {
-        Timed tm(c, prof, IGS_K_UPDATE, j, cycles, 8.0 * dn * (j + 1) + 8.0 * dn + 16.0 * dn);
+        Timed tm(c, pmask, IGS_K_UPDATE, j, cycles, 8.0 * dn * (j + 1) + 8.0 * dn + 16.0 * dn);
         HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_iters, s));
       }
     }
     if (!final_check) {
       HIP_OR_FAIL(c, igs::launch_lsq(w, m, s));
-      Timed tm(c, prof, IGS_K_XUPDATE, -1, cycles, 0.0);
+      Timed tm(c, pmask, IGS_K_XUPDATE, -1, cycles, 0.0);
       HIP_OR_FAIL(c, igs::launch_xupdate(w, n, x, s));
     }
     HIP_OR_FAIL(c, hipMemcpyAsync(c->h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -555,9 +557,14 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       c->J_first = J;
       c->ldh_first = w.ldh;
       if (J > 0) {
+        // H is packed by columns on the device: column k holds rows 0..k+1
+        const size_t packed = (size_t)J * (J + 3) / 2;
+        std::vector<double> hp(packed);
+        HIP_OR_FAIL(c, hipMemcpy(hp.data(), w.H, sizeof(double) * packed, hipMemcpyDeviceToHost));
         c->H_first.assign((size_t)w.ldh * J, 0.0);
-        HIP_OR_FAIL(c, hipMemcpy(c->H_first.data(), w.H, sizeof(double) * w.ldh * J,
-                                 hipMemcpyDeviceToHost));
+        for (int k = 0; k < J; ++k)
+          for (int i = 0; i <= k + 1; ++i)
+            c->H_first[(size_t)k * w.ldh + i] = hp[(size_t)k * (k + 3) / 2 + i];
       }
       if (o.keep_first_basis) {
         const size_t cols = (size_t)J + 1;

@@ -31,7 +31,7 @@ EXPORTED = (
 class IgsOpts(ctypes.Structure):
     _fields_ = [("maxit", c_int64), ("lagnorm_tau", c_double), ("final_basis_vector", c_int),
                 ("profile", c_int), ("max_cycles", c_int), ("keep_first_basis", c_int),
-                ("reserved", c_int * 6)]
+                ("profile_kernels", c_int), ("reserved", c_int * 5)]
 
 
 class IgsInfo(ctypes.Structure):

@@ -113,13 +113,15 @@ def _basis(torch, n, ncols, seed, ldv=None):
     return Vt, torch.tensor(host, device="cuda")
 
 
+@pytest.mark.parametrize("pad", [13, 64], ids=["ld_odd", "ld_even"])
 @pytest.mark.parametrize("j", [0, 1, 5, 8, 15, 16, 17, 31, 60, 127, 200])
 @pytest.mark.parametrize("n", [100_003, 4_099])
-def test_reduce_matches_oracle(torch, n, j):
+def test_reduce_matches_oracle(torch, n, j, pad):
+    """Odd leading dimension: 8-byte path; even: 16-byte row-pair path."""
     from paper_2205_07805_amd import igs
-    print(f"reduce n={n} j={j}", flush=True)
+    print(f"reduce n={n} j={j} ldv=n+{pad}", flush=True)
     ctx_small = ctx_of_size(n)
-    ldv = n + 13
+    ldv = n + pad
     Vt, Vd = _basis(torch, n, j + 1, seed=j + n, ldv=ldv)
     z = W.rhs_normal(n, j)
     zd = torch.tensor(z, device="cuda")
@@ -139,13 +141,14 @@ def test_reduce_matches_oracle(torch, n, j):
     assert np.array_equal(P2, P)
 
 
+@pytest.mark.parametrize("pad", [3, 64], ids=["ld_odd", "ld_even"])
 @pytest.mark.parametrize("j", [0, 1, 7, 33, 60])
-@pytest.mark.parametrize("n", [100_003, 1_025])
-def test_update_matches_oracle(torch, n, j):
+@pytest.mark.parametrize("n", [100_003, 1_025, 4_096])
+def test_update_matches_oracle(torch, n, j, pad):
     from paper_2205_07805_amd import igs
-    print(f"update n={n} j={j}", flush=True)
+    print(f"update n={n} j={j} ldv=n+{pad}", flush=True)
     ctx_small = ctx_of_size(n)
-    ldv = n + 3
+    ldv = n + pad
     Vt, Vd = _basis(torch, n, j + 2, seed=3 * j + n, ldv=ldv)
     rng = np.random.default_rng(j)
     t = rng.standard_normal(j) * 1e-3
