@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -127,6 +129,15 @@ def main():
     a, b = W.make_convdiff3d(args.grid, 50.0)
     log(f"[bench] generated n={a.n} nnz={a.nnz} in {time.perf_counter() - t0:.1f}s")
     workload = f"convdiff3d_N{args.grid}_Pe50_gmres{args.restart}_tol{args.tol:g}"
+
+    if args.copy_calibration:
+        src = torch.ones(32 * 2**20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {src.numel() * 8} bytes read and written per launch")
+        del src, dst
 
     s = Solver(a)
     b_d = torch.as_tensor(b, device=dev)

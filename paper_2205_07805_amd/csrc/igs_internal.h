@@ -11,9 +11,9 @@ constexpr int kReduceThreads = 512;     // 8 waves per block in the fused reduct
 constexpr int kReduceWaves = kReduceThreads / kWave;
 constexpr int kUpdateThreads = 256;
 constexpr int kUpdateRows = 4;          // rows per thread in the update / x-update passes
-constexpr int kGroup = 32;              // blocks per first-level group of a grid reduction
-constexpr int kMaxBlocks = 2048;
-constexpr int kMaxGroups = kMaxBlocks / kGroup;
+constexpr int kMaxBlocks = 2048;        // most blocks of a kernel that writes partial sums
+constexpr int kMaxGroups = 64;          // rows of the group-partial buffer (8 are used; the rest
+                                        // is scratch for the explicit-norm fallback)
 
 // How a restart cycle ended (mirrors IGS_CYCLE_* in igs.h).
 enum CycleStatus : int {

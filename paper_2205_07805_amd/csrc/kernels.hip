@@ -94,18 +94,21 @@ __device__ void sum_rows(const double* src, int pstride, int cnt, int nv, double
 // Deterministic grid-wide sum of nv per-block values.
 // Precondition: wave 0 of every block has written its block's values to
 // part[blockIdx.x * pstride + v], v < nv (only wave 0 writes, so that its one
-// release fence publishes all of them).  Blocks are combined in groups of
-// kGroup -- the last block of a group to arrive sums that group -- and the
-// last group sums the group totals.  Returns true in exactly one block; there
-// out[v] (shared memory) holds the totals.  scratch: shared memory of
-// max(blockDim.x, nv) doubles, disjoint from out.
+// release fence publishes all of them).  First level: the blocks are split
+// into up to 8 groups by blockIdx % 8 -- the blocks of one group then run on
+// one XCD under the hardware's round-robin dispatch, so a group's partials
+// and its counter stay in one L2 (the result does not depend on where blocks
+// run) -- and the last block of a group to arrive sums that group.  Second
+// level: the last group sums the group totals.  Returns true in exactly one
+// block; there out[v] (shared memory) holds the totals.  scratch: shared
+// memory of max(blockDim.x, nv) doubles, disjoint from out.
 __device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
                                  int nv, double* out, double* scratch) {
   __shared__ int s_last;
   const int nb = gridDim.x;
-  const int g = blockIdx.x / kGroup;
-  const int ngroups = (nb + kGroup - 1) / kGroup;
-  const int gsize = min(kGroup, nb - g * kGroup);
+  const int ngroups = nb < 8 ? nb : 8;
+  const int g = blockIdx.x % ngroups;
+  const int gsize = (nb - g + ngroups - 1) / ngroups;
   if (threadIdx.x < kWave) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (threadIdx.x == 0) s_last = (atomicAdd(&tickets[g], 1u) == (unsigned)(gsize - 1));
@@ -113,7 +116,8 @@ __device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsig
   __syncthreads();
   if (!s_last) return false;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  sum_rows(part + (size_t)g * kGroup * pstride, pstride, gsize, nv, out, scratch);
+  // members of group g: blocks g, g + ngroups, g + 2 ngroups, ...
+  sum_rows(part + (size_t)g * pstride, pstride * ngroups, gsize, nv, out, scratch);
   if (threadIdx.x < kWave) {
     for (int v = threadIdx.x; v < nv; v += kWave) gpart[(size_t)g * pstride + v] = out[v];
     if (threadIdx.x == 0) tickets[g] = 0u;
@@ -351,14 +355,32 @@ hipError_t launch_bnorm(const double* b, const double* x, long long n, const Wor
 // ---------------------------------------------------------------------------
 
 __device__ double givens_column(const Work& w, int c, double* col, const double* scs,
-                                const double* ssn) {
-  for (int i = 0; i < c; ++i) {
-    const double a = col[i];
-    const double b = col[i + 1];
-    col[i] = scs[i] * a + ssn[i] * b;
-    col[i + 1] = -ssn[i] * a + scs[i] * b;
+                                const double* ssn, double gc) {
+  // Rotation i mixes entries i and i+1.  The running entry `cur` carries the
+  // dependency chain; the inputs col[i+1], cs[i], sn[i] do not depend on it and
+  // are loaded in groups of eight ahead of the arithmetic.
+  double cur = col[0];
+  int i = 0;
+  for (; i + 8 <= c; i += 8) {
+    double nb[8], cc[8], ss[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      nb[q] = col[i + q + 1];
+      cc[q] = scs[i + q];
+      ss[q] = ssn[i + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      col[i + q] = cc[q] * cur + ss[q] * nb[q];
+      cur = -ss[q] * cur + cc[q] * nb[q];
+    }
   }
-  const double a = col[c];
+  for (; i < c; ++i) {
+    const double nb = col[i + 1];
+    col[i] = scs[i] * cur + ssn[i] * nb;
+    cur = -ssn[i] * cur + scs[i] * nb;
+  }
+  const double a = cur;
   const double b = col[c + 1];
   const double d = hypot(a, b);
   double cs = 1.0, sn = 0.0;
@@ -370,7 +392,6 @@ __device__ double givens_column(const Work& w, int c, double* col, const double*
   col[c + 1] = 0.0;
   w.cs[c] = cs;
   w.sn[c] = sn;
-  const double gc = w.g[c];
   w.g[c + 1] = -sn * gc;
   w.g[c] = cs * gc;
   return fabs(sn * gc);
@@ -414,26 +435,18 @@ __host__ __device__ __forceinline__ size_t stage_count(int j) {
 
 // Finish Hessenberg column j-1 with subdiagonal gamma: store H and the rotated
 // column, apply the rotation, and run the breakdown test.  hcol (shared or
-// global) holds H[0:j, j-1]; scratch needs 2*j doubles.  Called by all
-// threads of a block.  Returns 1 on breakdown, 0 otherwise; ctl->gabs is
-// updated.
-__device__ int finish_column(const Work& w, int j, double* hcol, double gamma, double* scratch,
-                             long long n) {
+// global, j+1 entries) holds H[0:j, j-1]; scs/ssn hold the rotations 0..j-2
+// and gc the right-hand side entry g[j-1], all loaded by the caller.  Called
+// by all threads of a block.  Returns 1 on breakdown, 0 otherwise;
+// ctl->gabs is updated.
+__device__ int finish_column(const Work& w, int j, double* hcol, double gamma, const double* scs,
+                             const double* ssn, double gc, long long n) {
   __shared__ double s_hn;
   __shared__ int s_brk;
-  double* scs = scratch;
-  double* ssn = scratch + j;
   const int c = j - 1;
   double* hc = w.H + hess_col(c);
-  for (int i = threadIdx.x; i < j; i += blockDim.x) {
-    hc[i] = hcol[i];
-    if (i < c) {
-      scs[i] = w.cs[i];
-      ssn[i] = w.sn[i];
-    }
-  }
+  for (int i = threadIdx.x; i < j; i += blockDim.x) hc[i] = hcol[i];
   if (threadIdx.x == 0) hc[j] = gamma;
-  __syncthreads();
   if (threadIdx.x < kWave) {
     const double hn2 = wave_dot(hcol, hcol, j);
     if (threadIdx.x == 0) s_hn = sqrt(hn2);
@@ -441,7 +454,7 @@ __device__ int finish_column(const Work& w, int j, double* hcol, double gamma, d
   __syncthreads();
   if (threadIdx.x == 0) {
     hcol[j] = gamma;
-    const double gabs = givens_column(w, c, hcol, scs, ssn);
+    const double gabs = givens_column(w, c, hcol, scs, ssn, gc);
     w.ctl->gabs = gabs;
     const double eps = 2.220446049250313e-16;
     s_brk = (gamma <= (double)n * eps * s_hn) ? 1 : 0;
@@ -453,28 +466,113 @@ __device__ int finish_column(const Work& w, int j, double* hcol, double gamma, d
   return brk;
 }
 
+// Products with the small matrices T and H, computed by the whole block.
+// Ts / Hs are the packed T and H.  Staged (shared memory): one output per
+// thread, a sequential dot product over LDS, no cross-lane reduction.  Not
+// staged (global memory): one wave per output, coalesced loads and a wave sum.
+
+// y[i] = sum_{c <= i} T[i, c] x[c], i < j.
+template <bool STAGED>
+__device__ __forceinline__ void tri_matvec(const double* Ts, const double* x, double* y, int j) {
+  if constexpr (STAGED) {
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+      const double* trow = Ts + tri_row(i);
+      double a0 = 0.0, a1 = 0.0;
+      int c = 0;
+      for (; c + 1 <= i; c += 2) {
+        a0 = fma(trow[c], x[c], a0);
+        a1 = fma(trow[c + 1], x[c + 1], a1);
+      }
+      if (c <= i) a0 = fma(trow[c], x[c], a0);
+      y[i] = a0 + a1;
+    }
+  } else {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
+    for (int i = wave; i < j; i += nw) {
+      const double* trow = Ts + tri_row(i);
+      double acc = 0.0;
+      for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], x[c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) y[i] = acc;
+    }
+  }
+}
+
+// y[c] = -sum_{i = c..j-1} l[i] T[i, c], c < j.
+template <bool STAGED>
+__device__ __forceinline__ void tri_rowvec(const double* Ts, const double* l, double* y, int j) {
+  if constexpr (STAGED) {
+    for (int c = threadIdx.x; c < j; c += blockDim.x) {
+      double a0 = 0.0, a1 = 0.0;
+      int i = c;
+      for (; i + 1 < j; i += 2) {
+        a0 = fma(l[i], Ts[tri_row(i) + c], a0);
+        a1 = fma(l[i + 1], Ts[tri_row(i + 1) + c], a1);
+      }
+      if (i < j) a0 = fma(l[i], Ts[tri_row(i) + c], a0);
+      y[c] = -(a0 + a1);
+    }
+  } else {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
+    for (int c = wave; c < j; c += nw) {
+      double acc = 0.0;
+      for (int i = c + lane; i < j; i += kWave) acc = fma(l[i], Ts[tri_row(i) + c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) y[c] = -acc;
+    }
+  }
+}
+
+// y[i] = sum_{c = max(i-1,0)..j-2} H[i, c] x[c], i < j.
+template <bool STAGED>
+__device__ __forceinline__ void hess_matvec(const double* Hs, const double* x, double* y, int j) {
+  if constexpr (STAGED) {
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+      double a0 = 0.0, a1 = 0.0;
+      int c = i > 0 ? i - 1 : 0;
+      for (; c + 1 < j - 1; c += 2) {
+        a0 = fma(Hs[hess_col(c) + i], x[c], a0);
+        a1 = fma(Hs[hess_col(c + 1) + i], x[c + 1], a1);
+      }
+      if (c < j - 1) a0 = fma(Hs[hess_col(c) + i], x[c], a0);
+      y[i] = a0 + a1;
+    }
+  } else {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
+    for (int i = wave; i < j; i += nw) {
+      double acc = 0.0;
+      for (int c = (i > 0 ? i - 1 : 0) + lane; c < j - 1; c += kWave)
+        acc = fma(Hs[hess_col(c) + i], x[c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) y[i] = acc;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The small solve of iteration j, run by the last block of the reduction.
 // P[c] = V_c^T u, Q[c] = V_c^T z for c <= j (P[j] = u^T u, Q[j] = u^T z).
-// sm: shared scratch of 7 (j + 2) doubles, followed by stage_count(j) more.
+// sm: shared scratch of 7 (j + 2) doubles, followed (STAGED) by the staged
+// prefix of T and H, stage_count(j) doubles.
 // ---------------------------------------------------------------------------
 
+template <bool STAGED>
 __device__ void small_solve(const Work& w, long long n, int j, bool tail, const double* P,
                             const double* Q, double* sm) {
   Ctl* ctl = w.ctl;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = tid % kWave;
-  const int nw = blockDim.x / kWave;
   // shared scratch, each of length j + 2
   const int L1 = j + 2;
   double* st = sm;            // t (second sweep coefficients)
   double* shc = sm + L1;      // finished column j-1
   double* sr1 = sm + 2 * L1;  // new first-sweep coefficients
-  double* sx = sm + 3 * L1;   // temp
+  double* sx = sm + 3 * L1;   // t_prev / gamma_prev, then temporaries
   double* sl = sm + 4 * L1;   // new row of L
-  double* sgiv = sm + 5 * L1; // 2 * L1 for the rotations
-  __shared__ double s_gamma, s_pp;
+  double* scs = sm + 5 * L1;  // rotations cos 0..j-2
+  double* ssn = sm + 6 * L1;  // rotations sin 0..j-2
+  __shared__ double s_gamma, s_pp, s_gc, s_gprev;
   __shared__ int s_flag;
 
   const int gs = ctl->gs;
@@ -514,29 +612,35 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     return;
   }
 
-  // ---- T rows 0..j-1 and H columns 0..j-2 (staged in shared memory if small)
+  // ---- one batch of loads: T rows 0..j-1 and H columns 0..j-2 (staged), the
+  // previous coefficients, the rotations and g[j-1]
   const double* Ts = w.T;
   const double* Hs = w.H;
-  const size_t nstage = stage_count(j);
-  if (nstage) {
-    double* stg = sm + 7 * L1;
+  double* stg = sm + 7 * L1;
+  if constexpr (STAGED) {
     const size_t nT = tri_row(j);
     stage_copy(stg, w.T, nT);
-    stage_copy(stg + nT, w.H, nstage - nT);
-    __syncthreads();
+    stage_copy(stg + nT, w.H, hess_col(j - 1));
     Ts = stg;
     Hs = stg + nT;
   }
+  for (int i = tid; i < j; i += blockDim.x) {
+    shc[i] = w.coef_r1[i];                 // r1 of the previous iteration
+    if (i < j - 1) {
+      sx[i] = w.coef_t[i];                 // t of the previous iteration
+      scs[i] = w.cs[i];
+      ssn[i] = w.sn[i];
+    }
+  }
+  if (tid == 0) {
+    s_gc = w.g[j - 1];
+    s_gprev = ctl->gamma_prev;
+  }
+  __syncthreads();
 
   // ---- second sweep t = (I + L_{0:j,0:j})^{-1} p = T_j p  (gs = 2) ----------
   if (gs == 2) {
-    for (int i = wave; i < j; i += nw) {
-      const double* trow = Ts + tri_row(i);
-      double acc = 0.0;
-      for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], P[c], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) st[i] = acc;
-    }
+    tri_matvec<STAGED>(Ts, P, st, j);
   } else {
     for (int i = tid; i < j; i += blockDim.x) st[i] = 0.0;
   }
@@ -545,21 +649,16 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     if (lane == 0) s_pp = pp;
   }
   {
-    const double igp = 1.0 / ctl->gamma_prev;
-    for (int i = tid; i < j; i += blockDim.x) {
-      shc[i] = w.coef_r1[i];                       // r1 of the previous iteration
-      if (i < j - 1) sx[i] = w.coef_t[i] * igp;    // t_prev / gamma_prev
-    }
+    const double igp = 1.0 / s_gprev;
+    for (int i = tid; i < j - 1; i += blockDim.x) sx[i] *= igp;   // t_prev / gamma_prev
   }
   __syncthreads();
 
   // ---- finished column j-1:  r1_prev + t - H[0:j, 0:j-1] (t_prev / gamma_prev)
-  for (int i = tid; i < j; i += blockDim.x) {
-    double acc = 0.0;
-    if (gs == 2) {
-      for (int c = (i > 0 ? i - 1 : 0); c < j - 1; ++c) acc = fma(Hs[hess_col(c) + i], sx[c], acc);
-    }
-    shc[i] = shc[i] + st[i] - acc;
+  if (gs == 2) {
+    hess_matvec<STAGED>(Hs, sx, sr1, j);   // sr1 is free until the first sweep below
+    __syncthreads();
+    for (int i = tid; i < j; i += blockDim.x) shc[i] = shc[i] + st[i] - sr1[i];
   }
   __syncthreads();
 
@@ -596,7 +695,7 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
   const double ig = 1.0 / gamma;
 
   // ---- Hessenberg column, Givens rotation, breakdown test --------------------
-  const int brk = finish_column(w, j, shc, gamma, sgiv, n);
+  const int brk = finish_column(w, j, shc, gamma, scs, ssn, s_gc, n);
   if (brk) {
     if (tid == 0) {
       ctl->status = kBreakdown;
@@ -614,13 +713,11 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     w.L[(size_t)c * w.ldt + j] = l;
   }
   __syncthreads();
+  tri_rowvec<STAGED>(Ts, sl, sx, j);
+  __syncthreads();
   {
     double* trow = w.T + tri_row(j);
-    for (int c = tid; c < j; c += blockDim.x) {
-      double acc = 0.0;
-      for (int i = c; i < j; ++i) acc = fma(sl[i], Ts[tri_row(i) + c], acc);
-      trow[c] = -acc;
-    }
+    for (int c = tid; c < j; c += blockDim.x) trow[c] = sx[c];
     if (tid == 0) trow[j] = 1.0;
   }
 
@@ -662,13 +759,7 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     // r1 = (I + L_{0:j+1,0:j+1})^{-1} [q/gamma ; beta/gamma^2]
     for (int c = tid; c < j; c += blockDim.x) sx[c] = Q[c] * ig;
     __syncthreads();
-    for (int i = wave; i < j; i += nw) {
-      const double* trow = Ts + tri_row(i);
-      double acc = 0.0;
-      for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], sx[c], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) sr1[i] = acc;
-    }
+    tri_matvec<STAGED>(Ts, sx, sr1, j);
     __syncthreads();
     if (wave == 0) {
       const double d = wave_dot(sl, sr1, j);
@@ -867,7 +958,10 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
     for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) raw_out[v] = lds[v];
     return;
   }
-  small_solve(w, n, j, !with_z, lds, lds + ncol, lds + 2 * ncol);
+  if (stage_count(j) > 0)
+    small_solve<true>(w, n, j, !with_z, lds, lds + ncol, lds + 2 * ncol);
+  else
+    small_solve<false>(w, n, j, !with_z, lds, lds + ncol, lds + 2 * ncol);
 }
 
 // Shared memory of the fused reduction: the wave partials; then the totals
@@ -1126,9 +1220,19 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   // the group totals are consumed: reuse that global buffer as scratch
   double* scratch = w.gpart;
   double* hcol = scratch;
-  for (int i = threadIdx.x; i < j; i += blockDim.x) hcol[i] = w.H[hess_col(j - 1) + i];
+  double* fcs = scratch + (j + 2);
+  double* fsn = fcs + (j + 2);
+  __shared__ double s_gc;
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    hcol[i] = w.H[hess_col(j - 1) + i];
+    if (i < j - 1) {
+      fcs[i] = w.cs[i];
+      fsn[i] = w.sn[i];
+    }
+  }
+  if (threadIdx.x == 0) s_gc = w.g[j - 1];
   __syncthreads();
-  const int brk = finish_column(w, j, hcol, gamma, scratch + (j + 2), n);
+  const int brk = finish_column(w, j, hcol, gamma, fcs, fsn, s_gc, n);
   if (threadIdx.x == 0) {
     Ctl* c = w.ctl;
     c->J = j;
