@@ -204,7 +204,9 @@ hipEvent_t next_event(igs_ctx* c) {
     return e;
   }
   hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing events without the system-scope fence: the times are read by the
+  // host after a stream synchronisation, never through host-visible memory
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   c->event_pool.push_back(e);
   return e;
 }
