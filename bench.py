@@ -17,7 +17,6 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,22 +29,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Arnoldi iters/s + HBM GB/s; batched solves/s, p50/p99 latency at β≤1e-12"
-KERNEL_SRC = os.path.join(ROOT, "paper_2205_07805_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_convdiff3d_N128_gmres60.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernels changed since the counters were taken."""
+    from paper_2205_07805_amd.profiling import kernel_source_sha
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
