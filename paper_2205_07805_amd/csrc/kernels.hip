@@ -18,6 +18,10 @@
 
 #include <math.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace igs {
 
 constexpr int LPR_RPG_MAX = 4;  // rows per lane group for rows of <= 8 lanes
@@ -26,10 +30,44 @@ constexpr int LPR_RPG_MAX = 4;  // rows per lane group for rows of <= 8 lanes
 // helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+// Cross-lane sums with DPP moves (register to register, no LDS round trip).
+// A double moves as its two 32-bit halves.  dpp_ctrl values (GFX9 encoding):
+// quad_perm [1,0,3,2] = 0xB1 and [2,3,0,1] = 0x4E exchange lanes i^1 and i^2
+// inside each group of 4; row_half_mirror = 0x141 maps lane i to 7-i inside
+// each group of 8; row_mirror = 0x140 maps lane i to 15-i inside each row of
+// 16.  After the steps up to a group size every lane of the group holds the
+// group's sum, added in the same order in every lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16); every lane of a
+// group gets the group's sum.  All lanes of the wave must be active.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_move<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_move<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_move<0x141>(v);
+  if constexpr (G >= 16) v += dpp_move<0x140>(v);
   return v;
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane (a wave-uniform
+// value).  All lanes of the wave must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group_sum<16>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Two consecutive rows of a column as one 16-byte access.
@@ -158,7 +196,9 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
                                                        double* __restrict__ y,
                                                        const double* __restrict__ bsub,
                                                        const Ctl* __restrict__ gate) {
-  if (gate != nullptr && !ctl_active(gate)) return;
+  // the gate is read together with the row bounds, so its latency overlaps
+  // theirs; nothing is stored before it is checked
+  const int act = (gate != nullptr) ? load_agent(&gate->active) : 1;
   const long long lb = xcd_block(blockIdx.x, gridDim.x);
   const long long grp = (lb * blockDim.x + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
@@ -167,6 +207,7 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
   int bnd[RPG + 1];
 #pragma unroll
   for (int q = 0; q <= RPG; ++q) bnd[q] = rp[min(row0 + q, n)];
+  if (!act) return;
   int cidx[RPG];
   double val[RPG];
 #pragma unroll
@@ -184,8 +225,12 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
     for (int k = bnd[q] + lane + LPR; k < bnd[q + 1]; k += LPR) acc[q] = fma(va[k], x[ci[k]], acc[q]);
 #pragma unroll
   for (int q = 0; q < RPG; ++q) {
+    if constexpr (LPR <= 16) {
+      acc[q] = group_sum<LPR>(acc[q]);
+    } else {
 #pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, LPR);
+      for (int off = LPR / 2; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, LPR);
+    }
   }
   if constexpr (LPR >= RPG) {
     // lane q of the group stores row q: one coalesced store per wave
@@ -477,14 +522,20 @@ __device__ __forceinline__ void tri_matvec(const double* Ts, const double* x, do
   if constexpr (STAGED) {
     for (int i = threadIdx.x; i < j; i += blockDim.x) {
       const double* trow = Ts + tri_row(i);
-      double a0 = 0.0, a1 = 0.0;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
       int c = 0;
-      for (; c + 1 <= i; c += 2) {
-        a0 = fma(trow[c], x[c], a0);
-        a1 = fma(trow[c + 1], x[c + 1], a1);
+      for (; c + 8 <= i + 1; c += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = trow[c + q];
+          b[q] = x[c + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q & 3] = fma(a[q], b[q], acc[q & 3]);
       }
-      if (c <= i) a0 = fma(trow[c], x[c], a0);
-      y[i] = a0 + a1;
+      for (; c <= i; ++c) acc[0] = fma(trow[c], x[c], acc[0]);
+      y[i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
   } else {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
@@ -503,14 +554,20 @@ template <bool STAGED>
 __device__ __forceinline__ void tri_rowvec(const double* Ts, const double* l, double* y, int j) {
   if constexpr (STAGED) {
     for (int c = threadIdx.x; c < j; c += blockDim.x) {
-      double a0 = 0.0, a1 = 0.0;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
       int i = c;
-      for (; i + 1 < j; i += 2) {
-        a0 = fma(l[i], Ts[tri_row(i) + c], a0);
-        a1 = fma(l[i + 1], Ts[tri_row(i + 1) + c], a1);
+      for (; i + 8 <= j; i += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = l[i + q];
+          b[q] = Ts[tri_row(i + q) + c];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q & 3] = fma(a[q], b[q], acc[q & 3]);
       }
-      if (i < j) a0 = fma(l[i], Ts[tri_row(i) + c], a0);
-      y[c] = -(a0 + a1);
+      for (; i < j; ++i) acc[0] = fma(l[i], Ts[tri_row(i) + c], acc[0]);
+      y[c] = -((acc[0] + acc[1]) + (acc[2] + acc[3]));
     }
   } else {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
@@ -528,14 +585,20 @@ template <bool STAGED>
 __device__ __forceinline__ void hess_matvec(const double* Hs, const double* x, double* y, int j) {
   if constexpr (STAGED) {
     for (int i = threadIdx.x; i < j; i += blockDim.x) {
-      double a0 = 0.0, a1 = 0.0;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
       int c = i > 0 ? i - 1 : 0;
-      for (; c + 1 < j - 1; c += 2) {
-        a0 = fma(Hs[hess_col(c) + i], x[c], a0);
-        a1 = fma(Hs[hess_col(c + 1) + i], x[c + 1], a1);
+      for (; c + 8 <= j - 1; c += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = Hs[hess_col(c + q) + i];
+          b[q] = x[c + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q & 3] = fma(a[q], b[q], acc[q & 3]);
       }
-      if (c < j - 1) a0 = fma(Hs[hess_col(c) + i], x[c], a0);
-      y[i] = a0 + a1;
+      for (; c < j - 1; ++c) acc[0] = fma(Hs[hess_col(c) + i], x[c], acc[0]);
+      y[i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
   } else {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
@@ -789,35 +852,184 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
 // reduces across lanes only once per column group.
 
 struct ReduceShape {
-  int cpw, wc, wr, nblocks;
+  int cpw;   // columns per group (the last group may have fewer)
+  int tcpw;  // template width: the power of two >= cpw
+  int wc, wr;
+  int nblocks;
   long long rows_per_block;
 };
 
-static ReduceShape reduce_shape(long long n, int ncol) {
-  ReduceShape s;
-  int cpw = 1;
-  const int want = (ncol + kReduceWaves - 1) / kReduceWaves;
-  while (cpw < want && cpw < 16) cpw *= 2;
-  const int nchunk = (ncol + cpw - 1) / cpw;
-  s.cpw = cpw;
-  s.wc = nchunk < kReduceWaves ? nchunk : kReduceWaves;
-  s.wr = kReduceWaves / s.wc;
-  long long nb = (n + 511) / 512;
-  if (nb > 512) nb = 512;
-  if (nb < 1) nb = 1;
-  long long rpb = (n + nb - 1) / nb;
-  rpb = (rpb + 127) / 128 * 128;  // even row pairs per block
-  nb = (n + rpb - 1) / rpb;
-  s.nblocks = (int)nb;
-  s.rows_per_block = rpb;
+// Column groups x row slices for the 8 waves of a block: groups of cpw <= 8
+// columns, wc groups side by side and wr = 8 / wc row slices.  Among
+// wc in {1, 2, 4, 8} take the one whose busiest wave streams the fewest
+// values per row, (cpw + 2) / wr: its columns plus u and z.  Beyond 64
+// columns the 8 waves loop over groups of 8.
+static ReduceShape reduce_columns(int ncol) {
+  ReduceShape s{8, 8, kReduceWaves, 1, 0, 0};
+  double best = 1e30;
+  for (int wc = 1; wc <= kReduceWaves; wc *= 2) {
+    const int cpw = (ncol + wc - 1) / wc;
+    if (cpw > 8) continue;
+    const int wr = kReduceWaves / wc;
+    const double cost = (double)(cpw + 2) / wr;
+    if (cost < best) {
+      best = cost;
+      s.cpw = cpw;
+      s.wc = wc;
+      s.wr = wr;
+    }
+  }
+  s.tcpw = 1;
+  while (s.tcpw < s.cpw) s.tcpw *= 2;
   return s;
 }
 
-int reduce_grid(long long n) { return reduce_shape(n, 1).nblocks; }
+// Rows per block (a multiple of 128, so that row pairs and 64-lane steps tile
+// a block's range) for at most max_blocks blocks.
+static void reduce_rows(ReduceShape& s, long long n, int max_blocks) {
+  long long nb = (n + 127) / 128;
+  if (nb > max_blocks) nb = max_blocks;
+  if (nb < 1) nb = 1;
+  long long rpb = (n + nb - 1) / nb;
+  rpb = (rpb + 127) / 128 * 128;
+  s.rows_per_block = rpb;
+  s.nblocks = (int)((n + rpb - 1) / rpb);
+}
 
-template <int CPW, bool VEC>
+
+// One wave's share of the fused reduction for NC consecutive columns of V
+// (starting at vb): over the rows of its slice of [r0, r1),
+// ap[c] += V[r, c] u[r] and (Z) aq[c] += V[r, c] z[r].  NC and Z are
+// compile-time, so every load of a row step is unconditional and the whole
+// step is in flight before the first FMA.
+template <int NC, bool VEC, bool Z>
+__device__ __forceinline__ void stream_cols(const double* __restrict__ vb, long long ldv,
+                                            const double* __restrict__ u,
+                                            const double* __restrict__ z, long long r0,
+                                            long long r1, int rw, int wr, int lane, double* ap,
+                                            double* aq) {
+  if constexpr (VEC) {
+    // Lane owns rows (r, r+1): 16-byte loads, V non-temporal.  Two-stage
+    // software pipeline: the loads of the next row step are issued before
+    // the FMAs of the current one, so a wave always has a step in flight.
+    const long long step = 2LL * wr * kWave;
+    long long r = r0 + 2LL * ((long long)rw * kWave + lane);
+    // Two register stages A and B alternate roles (no copies between them,
+    // which would force a wait on the loads in flight).  Without a next step
+    // the current rows are loaded again and not used, so the loads stay
+    // unconditional and each wait covers only the step being consumed.
+    dvec2 ua = {0.0, 0.0}, za = {0.0, 0.0}, va[NC];
+    dvec2 ub = {0.0, 0.0}, zb = {0.0, 0.0}, vn[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) va[c] = vn[c] = dvec2{0.0, 0.0};
+    auto load = [&](dvec2& uu, dvec2& zz, dvec2* vv, long long rr) {
+      uu = ld2(u + rr);
+      if constexpr (Z) zz = ld2(z + rr);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) vv[c] = ld_stream2(vb + (size_t)c * ldv + rr);
+    };
+    auto consume = [&](const dvec2& uu, const dvec2& zz, const dvec2* vv) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        ap[c] = fma(vv[c].x, uu.x, ap[c]);
+        ap[c] = fma(vv[c].y, uu.y, ap[c]);
+        if constexpr (Z) {
+          aq[c] = fma(vv[c].x, zz.x, aq[c]);
+          aq[c] = fma(vv[c].y, zz.y, aq[c]);
+        }
+      }
+    };
+    if (r + 1 < r1) load(ua, za, va, r);
+    while (r + 1 < r1) {
+      long long rn = r + step;
+      load(ub, zb, vn, (rn + 1 < r1) ? rn : r);
+      consume(ua, za, va);
+      r = rn;
+      if (!(r + 1 < r1)) break;
+      rn = r + step;
+      load(ua, za, va, (rn + 1 < r1) ? rn : r);
+      consume(ub, zb, vn);
+      r = rn;
+    }
+    // an odd last row of the block's range
+    if (r < r1) {
+      const double uv = u[r];
+      const double zv = Z ? z[r] : 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double v = vb[(size_t)c * ldv + r];
+        ap[c] = fma(v, uv, ap[c]);
+        if constexpr (Z) aq[c] = fma(v, zv, aq[c]);
+      }
+    }
+  } else {
+    // any alignment: 8-byte loads, U row steps
+    constexpr int U = (NC >= 8) ? 1 : ((NC >= 4) ? 2 : 4);
+    const long long step = (long long)wr * kWave;
+    long long r = r0 + (long long)rw * kWave + lane;
+    for (; r + (U - 1) * step < r1; r += U * step) {
+      double uu[U], zz[U], vv[U][NC];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        uu[q] = u[r + q * step];
+        if constexpr (Z) zz[q] = z[r + q * step];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) vv[q][c] = vb[(size_t)c * ldv + r + q * step];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          ap[c] = fma(vv[q][c], uu[q], ap[c]);
+          if constexpr (Z) aq[c] = fma(vv[q][c], zz[q], aq[c]);
+        }
+      }
+    }
+    for (; r < r1; r += step) {
+      const double uv = u[r];
+      const double zv = Z ? z[r] : 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double v = vb[(size_t)c * ldv + r];
+        ap[c] = fma(v, uv, ap[c]);
+        if constexpr (Z) aq[c] = fma(v, zv, aq[c]);
+      }
+    }
+  }
+}
+
+// The partial column group (nc < CPW columns, the last one) dispatches to the
+// instantiation for its exact width.
+template <int CPW, bool VEC, bool Z>
+__device__ __forceinline__ void stream_group(int nc, const double* __restrict__ vb, long long ldv,
+                                             const double* __restrict__ u,
+                                             const double* __restrict__ z, long long r0,
+                                             long long r1, int rw, int wr, int lane, double* ap,
+                                             double* aq) {
+  if (nc == CPW) {
+    stream_cols<CPW, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq);
+    return;
+  }
+  if constexpr (CPW > 1) {
+    switch (nc) {
+      case 1: stream_cols<1, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 2: if constexpr (CPW > 2) stream_cols<2, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 3: if constexpr (CPW > 3) stream_cols<3, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 4: if constexpr (CPW > 4) stream_cols<4, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 5: if constexpr (CPW > 5) stream_cols<5, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 6: if constexpr (CPW > 6) stream_cols<6, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 7: if constexpr (CPW > 7) stream_cols<7, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      default: break;
+    }
+  }
+}
+
+template <int CPW, bool VEC, bool Z>
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
-    Work w, long long n, int j, int with_z, long long rows_per_block, int wc, int wr,
+    Work w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr,
     const double* __restrict__ Vraw, long long ldv_raw, const double* __restrict__ zraw,
     double* __restrict__ raw_out) {
   extern __shared__ double lds[];
@@ -832,103 +1044,17 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
   const long long r0 = (long long)blockIdx.x * rows_per_block;
   const long long r1 = min(n, r0 + rows_per_block);
   const double* __restrict__ u = V + (size_t)j * ldv;
-  const int nchunk = (ncol + CPW - 1) / CPW;
+  const int nchunk = (ncol + cpw - 1) / cpw;
   const int cw = wave % wc;
   const int rw = wave / wc;
   if (rw < wr) {
     for (int ch = cw; ch < nchunk; ch += wc) {
-      const int c0 = ch * CPW;
-      const int nc = min(CPW, ncol - c0);
+      const int c0 = ch * cpw;
+      const int nc = min(cpw, ncol - c0);
       double ap[CPW], aq[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
-      const double* __restrict__ vb = V + (size_t)c0 * ldv;
-      long long r;
-      if constexpr (VEC) {
-        // lane owns rows (r, r+1): 16-byte non-temporal loads of V; U row
-        // steps are loaded before any is used (U*(CPW+2) loads in flight)
-        constexpr int U = (CPW >= 16) ? 1 : ((CPW >= 8) ? 2 : 4);
-        const long long step = 2LL * wr * kWave;
-        r = r0 + 2LL * ((long long)rw * kWave + lane);
-        for (; r + (U - 1) * step + 1 < r1; r += U * step) {
-          dvec2 uu[U], zz[U], vv[U][CPW];
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-            uu[q] = ld2(u + r + q * step);
-            zz[q] = with_z ? ld2(z + r + q * step) : dvec2{0.0, 0.0};
-          }
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-              vv[q][c] = (c < nc) ? ld_stream2(vb + (size_t)c * ldv + r + q * step) : dvec2{0.0, 0.0};
-          }
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c) {
-              ap[c] = fma(vv[q][c].x, uu[q].x, ap[c]);
-              ap[c] = fma(vv[q][c].y, uu[q].y, ap[c]);
-              aq[c] = fma(vv[q][c].x, zz[q].x, aq[c]);
-              aq[c] = fma(vv[q][c].y, zz[q].y, aq[c]);
-            }
-          }
-        }
-        // remaining rows one at a time (ragged end of the block's range)
-        for (long long rr = r; rr < r1; rr += step) {
-          for (long long r2 = rr; r2 < rr + 2 && r2 < r1; ++r2) {
-            const double uu = u[r2];
-            const double zz = with_z ? z[r2] : 0.0;
-#pragma unroll
-            for (int c = 0; c < CPW; ++c) {
-              if (c < nc) {
-                const double v = vb[(size_t)c * ldv + r2];
-                ap[c] = fma(v, uu, ap[c]);
-                aq[c] = fma(v, zz, aq[c]);
-              }
-            }
-          }
-        }
-      } else {
-        // any alignment: 8-byte loads, U row steps batched
-        constexpr int U = (CPW >= 16) ? 2 : ((CPW >= 4) ? 4 : 8);
-        const long long step = (long long)wr * kWave;
-        r = r0 + (long long)rw * kWave + lane;
-        for (; r + (U - 1) * step < r1; r += U * step) {
-          double uu[U], zz[U], vv[U][CPW];
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-            uu[q] = u[r + q * step];
-            zz[q] = with_z ? z[r + q * step] : 0.0;
-          }
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-              vv[q][c] = (c < nc) ? vb[(size_t)c * ldv + r + q * step] : 0.0;
-          }
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c) {
-              ap[c] = fma(vv[q][c], uu[q], ap[c]);
-              aq[c] = fma(vv[q][c], zz[q], aq[c]);
-            }
-          }
-        }
-        for (; r < r1; r += step) {
-          const double uu = u[r];
-          const double zz = with_z ? z[r] : 0.0;
-#pragma unroll
-          for (int c = 0; c < CPW; ++c) {
-            if (c < nc) {
-              const double v = vb[(size_t)c * ldv + r];
-              ap[c] = fma(v, uu, ap[c]);
-              aq[c] = fma(v, zz, aq[c]);
-            }
-          }
-        }
-      }
+      stream_group<CPW, VEC, Z>(nc, V + (size_t)c0 * ldv, ldv, u, z, r0, r1, rw, wr, lane, ap, aq);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         if (c < nc) {
@@ -959,9 +1085,9 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
     return;
   }
   if (stage_count(j) > 0)
-    small_solve<true>(w, n, j, !with_z, lds, lds + ncol, lds + 2 * ncol);
+    small_solve<true>(w, n, j, !Z, lds, lds + ncol, lds + 2 * ncol);
   else
-    small_solve<false>(w, n, j, !with_z, lds, lds + ncol, lds + 2 * ncol);
+    small_solve<false>(w, n, j, !Z, lds, lds + ncol, lds + 2 * ncol);
 }
 
 // Shared memory of the fused reduction: the wave partials; then the totals
@@ -975,32 +1101,76 @@ static size_t reduce_lds_bytes(const ReduceShape& s, int ncol) {
   return (m > c ? m : c) * sizeof(double);
 }
 
+// Blocks of `kernel` that are resident at once on the current device with
+// `threads` threads and `lds` bytes of dynamic shared memory (cached).
+static int resident_blocks(const void* kernel, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  const auto key = std::make_tuple(dev, kernel, threads, lds);
+  std::lock_guard<std::mutex> g(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per = 0;
+  if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess ||
+      per < 1)
+    per = 1;
+  const int r = cus * per;
+  cache[key] = r;
+  return r;
+}
+
+typedef void (*ReduceKernel)(Work, long long, int, long long, int, int, int, const double*,
+                             long long, const double*, double*);
+
+static ReduceKernel pick_reduce(int tcpw, bool vec, bool z) {
+  switch (tcpw * 4 + (vec ? 2 : 0) + (z ? 1 : 0)) {
+#define IGS_RED_CASE(C, VV, ZZ) \
+  case C * 4 + VV * 2 + ZZ: return reduce_kernel<C, VV, ZZ>;
+#define IGS_RED_CASES(C) \
+  IGS_RED_CASE(C, 0, 0) IGS_RED_CASE(C, 0, 1) IGS_RED_CASE(C, 1, 0) IGS_RED_CASE(C, 1, 1)
+    IGS_RED_CASES(1) IGS_RED_CASES(2) IGS_RED_CASES(4) IGS_RED_CASES(8)
+#undef IGS_RED_CASES
+#undef IGS_RED_CASE
+    default: return nullptr;
+  }
+}
+
 static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z,
                                   const double* Vraw, long long ldv_raw, const double* zraw,
                                   double* raw_out, hipStream_t s, int* nblocks_out) {
   const int ncol = j + 1;
-  const ReduceShape sh = reduce_shape(n, ncol);
+  ReduceShape sh = reduce_columns(ncol);
   const size_t lds = reduce_lds_bytes(sh, ncol);
-  if (nblocks_out) *nblocks_out = sh.nblocks;
   // 16-byte row pairs need an even leading dimension and aligned columns
   const double* Vp = raw_out ? Vraw : w.V;
   const double* zp = raw_out ? zraw : w.z;
   const long long ldv = raw_out ? ldv_raw : w.ldv;
   const bool vec = (ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
                    (reinterpret_cast<uintptr_t>(zp) % 16 == 0);
-  switch (sh.cpw * 2 + (vec ? 1 : 0)) {
-#define IGS_RED_CASE(C, VV)                                                                    \
-  case C * 2 + VV:                                                                             \
-    hipLaunchKernelGGL((reduce_kernel<C, VV>), dim3(sh.nblocks), dim3(kReduceThreads), lds, s, \
-                       w, n, j, with_z ? 1 : 0, sh.rows_per_block, sh.wc, sh.wr, Vraw, ldv_raw, \
-                       zraw, raw_out);                                                         \
-    break;
-    IGS_RED_CASE(1, 0) IGS_RED_CASE(2, 0) IGS_RED_CASE(4, 0) IGS_RED_CASE(8, 0) IGS_RED_CASE(16, 0)
-    IGS_RED_CASE(1, 1) IGS_RED_CASE(2, 1) IGS_RED_CASE(4, 1) IGS_RED_CASE(8, 1) IGS_RED_CASE(16, 1)
-#undef IGS_RED_CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  ReduceKernel k = pick_reduce(sh.tcpw, vec, with_z);
+  if (k == nullptr) return hipErrorInvalidValue;
+  // One round of resident blocks.  The grid (and so the summation order) is
+  // the one of the variant with z, so that the tail iteration, which has no
+  // z, forms V^T u exactly as the others do.
+  int cap = resident_blocks(reinterpret_cast<const void*>(pick_reduce(sh.tcpw, vec, true)),
+                            kReduceThreads, lds);
+  if (cap > kMaxBlocks) cap = kMaxBlocks;
+  reduce_rows(sh, n, cap);
+  if (nblocks_out) *nblocks_out = sh.nblocks;
+  Work wa = w;
+  long long na = n, rpb = sh.rows_per_block, ldva = ldv_raw;
+  int ja = j, cpw = sh.cpw, wc = sh.wc, wr = sh.wr;
+  const double* va = Vraw;
+  const double* za = zraw;
+  double* oa = raw_out;
+  void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &va, &ldva, &za, &oa};
+  return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(sh.nblocks), dim3(kReduceThreads),
+                         args, lds, s);
 }
 
 hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,
