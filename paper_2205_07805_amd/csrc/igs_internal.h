@@ -29,14 +29,19 @@ enum UpdateMode : int {
   kUpdFallback = 3   // lagged norm cancelled: w = u - V t, explicit ||w||, finish column
 };
 
-// Control block in device memory.  Written by the last block of the fused
-// reduction (and by the fallback update); read at the start of every step
-// kernel so that kernels queued after the end of a cycle do nothing.
+// Control block in device memory.  Written by block 0 of the update kernel
+// (and by the last block of the explicit-norm fallback); read at the start of
+// every step kernel so that kernels queued after the end of a cycle do
+// nothing.  end_iter is the iteration at which the cycle ended: a kernel of
+// iteration j runs only while end_iter >= j, so the other blocks of the
+// kernel that ends the cycle still do their share.
+constexpr int kNotEnded = 1 << 30;
+
 struct Ctl {
-  int active;          // 1 while the current cycle runs
+  int end_iter;        // kNotEnded while the current cycle runs
   int J;               // finished Hessenberg columns in the current cycle
   int status;          // CycleStatus
-  int mode;            // UpdateMode for iteration mode_iter
+  int mode;            // UpdateMode of iteration mode_iter (as decided by block 0)
   int mode_iter;       // iteration the mode applies to (-1: none)
   int breakdowns;
   int fallbacks;
@@ -52,7 +57,6 @@ struct Ctl {
   double lagnorm_tau;
   double rho;          // ||r0|| of the cycle
   double gabs;         // |g_J| after the last finished column
-  double inv_gamma;    // 1 / gamma_j for the update kernel
   double gamma_prev;   // gamma of the previous iteration
   int nonfinite_in;    // count of non-finite entries in b and x0
   int pad;
@@ -89,9 +93,15 @@ struct Work {
   Ctl* ctl;
 };
 
+// Groups of the first level of the deterministic grid reduction for a grid
+// of nb blocks (blocks b with the same b % 8 form a group).
+__host__ __device__ inline int reduce_groups(int nb) { return nb < 8 ? nb : 8; }
+
 // ---- launchers (kernels.hip) ------------------------------------------------
 
-hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, hipStream_t s);
+// gate: skip when the cycle ended before iteration j (nullptr: always run).
+hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, int j,
+                       hipStream_t s);
 hipError_t launch_residual(const Op& op, const double* b, const double* x, double* r,
                            const Work& w, long long its_before, long long maxit, int m,
                            int gs, int final_v, double tol, double tau, hipStream_t s);
@@ -99,7 +109,8 @@ hipError_t launch_bnorm(const double* b, const double* x, long long n, const Wor
                         hipStream_t s);
 hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,
                          int* nblocks_out);
-hipError_t launch_update(const Work& w, long long n, int j, int gs, hipStream_t s);
+// ngroups: the group totals the reduction of iteration j left in w.gpart.
+hipError_t launch_update(const Work& w, long long n, int j, int gs, int ngroups, hipStream_t s);
 hipError_t launch_lsq(const Work& w, int m, hipStream_t s);
 hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s);
 
@@ -110,6 +121,5 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
 hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
                              const double* t, const double* r1, double inv_gamma, hipStream_t s);
 
-int reduce_grid(long long n);
 
 }  // namespace igs

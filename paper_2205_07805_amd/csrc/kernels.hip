@@ -84,7 +84,8 @@ __device__ __forceinline__ int load_agent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool ctl_active(const Ctl* c) { return load_agent(&c->active) != 0; }
+// Does iteration j of the current cycle run (the cycle has not ended before it)?
+__device__ __forceinline__ bool ctl_runs(const Ctl* c, int j) { return load_agent(&c->end_iter) >= j; }
 
 // Blocks are dispatched round-robin over the 8 XCDs.  Give each XCD a
 // contiguous range of logical blocks so that the neighbour gathers of the
@@ -129,19 +130,21 @@ __device__ void sum_rows(const double* src, int pstride, int cnt, int nv, double
   __syncthreads();
 }
 
-// Deterministic grid-wide sum of nv per-block values.
+// Deterministic sums of nv per-block values, in two levels.
 // Precondition: wave 0 of every block has written its block's values to
 // part[blockIdx.x * pstride + v], v < nv (only wave 0 writes, so that its one
-// release fence publishes all of them).  First level: the blocks are split
-// into up to 8 groups by blockIdx % 8 -- the blocks of one group then run on
-// one XCD under the hardware's round-robin dispatch, so a group's partials
-// and its counter stay in one L2 (the result does not depend on where blocks
-// run) -- and the last block of a group to arrive sums that group.  Second
-// level: the last group sums the group totals.  Returns true in exactly one
-// block; there out[v] (shared memory) holds the totals.  scratch: shared
-// memory of max(blockDim.x, nv) doubles, disjoint from out.
-__device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
-                                 int nv, double* out, double* scratch) {
+// release fence publishes all of them).
+//
+// First level (group_reduce_last): the blocks are split into up to 8 groups
+// by blockIdx % 8 -- the blocks of one group then run on one XCD under the
+// hardware's round-robin dispatch, so a group's partials and its counter stay
+// in one L2 (the result does not depend on where blocks run) -- and the last
+// block of a group to arrive sums that group in a fixed order into gpart[g]
+// and resets the group's counter.  Returns true in that block, with out[v]
+// (shared memory) holding the group's totals.  scratch: shared memory of
+// max(blockDim.x, nv) doubles, disjoint from out.
+__device__ bool group_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
+                                  int nv, double* out, double* scratch) {
   __shared__ int s_last;
   const int nb = gridDim.x;
   const int ngroups = nb < 8 ? nb : 8;
@@ -159,6 +162,18 @@ __device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsig
   if (threadIdx.x < kWave) {
     for (int v = threadIdx.x; v < nv; v += kWave) gpart[(size_t)g * pstride + v] = out[v];
     if (threadIdx.x == 0) tickets[g] = 0u;
+  }
+  return true;
+}
+
+// Both levels: the last group to finish sums the group totals.  Returns true
+// in exactly one block; there out[v] holds the grid totals.
+__device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
+                                 int nv, double* out, double* scratch) {
+  __shared__ int s_last;
+  if (!group_reduce_last(part, gpart, pstride, tickets, nv, out, scratch)) return false;
+  const int ngroups = reduce_groups(gridDim.x);
+  if (threadIdx.x < kWave) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (threadIdx.x == 0) s_last = (atomicAdd(&tickets[kMaxGroups], 1u) == (unsigned)(ngroups - 1));
   }
@@ -195,10 +210,10 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
                                                        const double* __restrict__ x,
                                                        double* __restrict__ y,
                                                        const double* __restrict__ bsub,
-                                                       const Ctl* __restrict__ gate) {
+                                                       const Ctl* __restrict__ gate, int gate_j) {
   // the gate is read together with the row bounds, so its latency overlaps
   // theirs; nothing is stored before it is checked
-  const int act = (gate != nullptr) ? load_agent(&gate->active) : 1;
+  const int act = (gate != nullptr) ? (load_agent(&gate->end_iter) >= gate_j) : 1;
   const long long lb = xcd_block(blockIdx.x, gridDim.x);
   const long long grp = (lb * blockDim.x + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
@@ -257,8 +272,8 @@ __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const doub
                                                          const double* __restrict__ x,
                                                          double* __restrict__ y,
                                                          const double* __restrict__ bsub,
-                                                         const Ctl* __restrict__ gate) {
-  if (gate != nullptr && !ctl_active(gate)) return;
+                                                         const Ctl* __restrict__ gate, int gate_j) {
+  if (gate != nullptr && !ctl_runs(gate, gate_j)) return;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const long long row = (long long)blockIdx.x * (blockDim.x / kWave) + wave;
@@ -278,12 +293,12 @@ __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const doub
 }
 
 static hipError_t op_apply(const Op& op, const double* x, double* y, const double* bsub,
-                           const Ctl* gate, hipStream_t s) {
+                           const Ctl* gate, int gate_j, hipStream_t s) {
   if (op.dense) {
     const int rows_per_block = 4;
     const unsigned grid = (unsigned)((op.n + rows_per_block - 1) / rows_per_block);
     hipLaunchKernelGGL(gemv_dense_kernel, dim3(grid), dim3(256), 0, s, op.n, op.A, op.lda, x, y,
-                       bsub, gate);
+                       bsub, gate, gate_j);
     return hipGetLastError();
   }
   // lanes per row LPR (a power of two near the mean row length), rows per lane
@@ -298,7 +313,7 @@ static hipError_t op_apply(const Op& op, const double* x, double* y, const doubl
 #define IGS_SPMV_CASE(L, R)                                                                     \
   case L:                                                                                       \
     hipLaunchKernelGGL((spmv_csr_kernel<L, R>), dim3(grid), dim3(256), 0, s, op.n, op.row_ptr,  \
-                       op.col_idx, op.vals, x, y, bsub, gate);                                  \
+                       op.col_idx, op.vals, x, y, bsub, gate, gate_j);                          \
     break;
     IGS_SPMV_CASE(1, LPR_RPG_MAX) IGS_SPMV_CASE(2, LPR_RPG_MAX) IGS_SPMV_CASE(4, LPR_RPG_MAX)
     IGS_SPMV_CASE(8, LPR_RPG_MAX) IGS_SPMV_CASE(16, 2) IGS_SPMV_CASE(32, 1) IGS_SPMV_CASE(64, 1)
@@ -308,8 +323,9 @@ static hipError_t op_apply(const Op& op, const double* x, double* y, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, hipStream_t s) {
-  return op_apply(op, u, z, nullptr, gate, s);
+hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, int j,
+                       hipStream_t s) {
+  return op_apply(op, u, z, nullptr, gate, j, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,7 +335,7 @@ hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate
 __global__ void cycle_begin_kernel(Ctl* c, long long its_before, long long maxit, int m, int gs,
                                    int final_v, double tol, double tau) {
   if (threadIdx.x != 0) return;
-  c->active = 1;
+  c->end_iter = kNotEnded;
   c->J = 0;
   c->status = kRunning;
   c->mode = kUpdNone;
@@ -342,7 +358,7 @@ hipError_t launch_residual(const Op& op, const double* b, const double* x, doubl
                      final_v, tol, tau);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return op_apply(op, x, r, b, nullptr, s);
+  return op_apply(op, x, r, b, nullptr, 0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,95 +629,131 @@ __device__ __forceinline__ void hess_matvec(const double* Hs, const double* x, d
 }
 
 // ---------------------------------------------------------------------------
-// The small solve of iteration j, run by the last block of the reduction.
-// P[c] = V_c^T u, Q[c] = V_c^T z for c <= j (P[j] = u^T u, Q[j] = u^T z).
+// The small solve of iteration j, run by every block of the update kernel on
+// the totals of the fused reduction, P[c] = V_c^T u and Q[c] = V_c^T z for
+// c <= j (P[j] = u^T u, Q[j] = u^T z), held in shared memory.
+//
+// Every block forms what its share of the update needs: the second-sweep
+// vector t (in sm[0..j-1]), gamma, the first-sweep vector r1 (in
+// sm[2(j+2) .. 2(j+2)+j]) and the update mode.  The publishing block (pub)
+// also finishes Hessenberg column j-1, applies its Givens rotation, appends
+// the rows of L and T = (I + L)^{-1} (eq:block), runs the stopping tests and
+// writes the results and the control block.  All blocks read the same inputs
+// and run the same arithmetic, so their t, gamma and r1 agree bit for bit.
+// What the other blocks read from device memory (T rows < j, the cycle
+// constants of the control block) is disjoint from what the publisher writes
+// (T row j, the L row, H and R column j-1, cs/sn[j-1], g[j-1..j], the
+// coefficient vectors, the status fields of the control block); the inputs
+// only the publisher reads (previous coefficients, rotations, g[j-1], H
+// columns < j-1) are read before it writes.
+//
 // sm: shared scratch of 7 (j + 2) doubles, followed (STAGED) by the staged
-// prefix of T and H, stage_count(j) doubles.
+// prefix of T (all blocks) and H (publisher), stage_count(j) doubles.
 // ---------------------------------------------------------------------------
 
+struct StepCoefs {
+  int mode;   // UpdateMode of this block's share of the update
+  double ig;  // 1 / gamma
+};
+
 template <bool STAGED>
-__device__ void small_solve(const Work& w, long long n, int j, bool tail, const double* P,
-                            const double* Q, double* sm) {
+__device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, const double* P,
+                                 const double* Q, double* sm, bool pub) {
   Ctl* ctl = w.ctl;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = tid % kWave;
-  // shared scratch, each of length j + 2
   const int L1 = j + 2;
   double* st = sm;            // t (second sweep coefficients)
-  double* shc = sm + L1;      // finished column j-1
+  double* shc = sm + L1;      // finished column j-1 (publisher)
   double* sr1 = sm + 2 * L1;  // new first-sweep coefficients
   double* sx = sm + 3 * L1;   // t_prev / gamma_prev, then temporaries
   double* sl = sm + 4 * L1;   // new row of L
-  double* scs = sm + 5 * L1;  // rotations cos 0..j-2
-  double* ssn = sm + 6 * L1;  // rotations sin 0..j-2
+  double* scs = sm + 5 * L1;  // rotations cos 0..j-2 (publisher)
+  double* ssn = sm + 6 * L1;  // rotations sin 0..j-2 (publisher)
   __shared__ double s_gamma, s_pp, s_gc, s_gprev;
   __shared__ int s_flag;
 
   const int gs = ctl->gs;
   const int m = ctl->m;
+  // A block's share while the cycle may go on: v_j and u_{j+1}, also past a
+  // stop that only the publisher sees (columns j and j+1 are not used after
+  // it); at the tail iteration v_j only, and only on request.
+  const int run_mode = tail ? (ctl->final_v ? kUpdVOnly : kUpdNone) : kUpdNormal;
   const double alpha = P[j];
   const double beta = tail ? 0.0 : Q[j];
+  StepCoefs out{kUpdNone, 0.0};
 
   if (!isfinite(alpha) || !isfinite(beta)) {
-    if (tid == 0) {
+    if (pub && tid == 0) {
       ctl->status = kNonfinite;
       ctl->J = j > 0 ? j - 1 : 0;
-      ctl->active = 0;
+      ctl->end_iter = j;
+      ctl->mode = kUpdNone;
+      ctl->mode_iter = j;
     }
-    return;
+    return out;
   }
 
   if (j == 0) {
-    if (tid == 0) {
-      const double gamma = sqrt(alpha);
+    const double gamma = sqrt(alpha);
+    // converged at the start, or a check cycle after the iteration budget
+    const bool stop = (gamma <= ctl->tol_abs) || (ctl->its_before >= ctl->maxit);
+    out.ig = 1.0 / gamma;
+    if (tid == 0) sr1[0] = beta * out.ig * out.ig;
+    if (pub && tid == 0) {
       ctl->rho = gamma;
       ctl->gabs = gamma;
       w.g[0] = gamma;
-      if (gamma <= ctl->tol_abs) {
-        ctl->status = kConvStart;
+      if (stop) {
+        ctl->status = (gamma <= ctl->tol_abs) ? kConvStart : kMaxit;
         ctl->J = 0;
-        ctl->active = 0;
+        ctl->end_iter = 0;
+        ctl->mode = kUpdNone;
       } else {
         w.T[0] = 1.0;
-        const double ig = 1.0 / gamma;
-        w.coef_r1[0] = beta * ig * ig;
-        ctl->inv_gamma = ig;
+        w.coef_r1[0] = beta * out.ig * out.ig;
         ctl->gamma_prev = gamma;
-        ctl->mode = kUpdNormal;
-        ctl->mode_iter = 0;
+        ctl->mode = run_mode;
       }
+      ctl->mode_iter = 0;
     }
-    return;
+    __syncthreads();
+    out.mode = stop ? kUpdNone : run_mode;
+    return out;
   }
 
-  // ---- one batch of loads: T rows 0..j-1 and H columns 0..j-2 (staged), the
-  // previous coefficients, the rotations and g[j-1]
+  // ---- one batch of loads: T rows 0..j-1 (and, publisher, H columns 0..j-2)
+  // staged; publisher: the previous coefficients, the rotations and g[j-1]
   const double* Ts = w.T;
   const double* Hs = w.H;
-  double* stg = sm + 7 * L1;
   if constexpr (STAGED) {
+    double* stg = sm + 7 * L1;
     const size_t nT = tri_row(j);
     stage_copy(stg, w.T, nT);
-    stage_copy(stg + nT, w.H, hess_col(j - 1));
     Ts = stg;
-    Hs = stg + nT;
-  }
-  for (int i = tid; i < j; i += blockDim.x) {
-    shc[i] = w.coef_r1[i];                 // r1 of the previous iteration
-    if (i < j - 1) {
-      sx[i] = w.coef_t[i];                 // t of the previous iteration
-      scs[i] = w.cs[i];
-      ssn[i] = w.sn[i];
+    if (pub) {
+      stage_copy(stg + nT, w.H, hess_col(j - 1));
+      Hs = stg + nT;
     }
   }
-  if (tid == 0) {
-    s_gc = w.g[j - 1];
-    s_gprev = ctl->gamma_prev;
+  if (pub) {
+    for (int i = tid; i < j; i += blockDim.x) {
+      shc[i] = w.coef_r1[i];               // r1 of the previous iteration
+      if (i < j - 1) {
+        sx[i] = w.coef_t[i];               // t of the previous iteration
+        scs[i] = w.cs[i];
+        ssn[i] = w.sn[i];
+      }
+    }
+    if (tid == 0) {
+      s_gc = w.g[j - 1];
+      s_gprev = ctl->gamma_prev;
+    }
   }
   __syncthreads();
 
-  // ---- second sweep t = (I + L_{0:j,0:j})^{-1} p = T_j p  (gs = 2) ----------
+  // ---- second sweep t = (I + L_{0:j,0:j})^{-1} p = T_j p  (gs = 2), and p.p
   if (gs == 2) {
     tri_matvec<STAGED>(Ts, P, st, j);
   } else {
@@ -711,14 +763,14 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
     const double pp = wave_dot(P, P, j);
     if (lane == 0) s_pp = pp;
   }
-  {
+  if (pub) {
     const double igp = 1.0 / s_gprev;
     for (int i = tid; i < j - 1; i += blockDim.x) sx[i] *= igp;   // t_prev / gamma_prev
   }
   __syncthreads();
 
-  // ---- finished column j-1:  r1_prev + t - H[0:j, 0:j-1] (t_prev / gamma_prev)
-  if (gs == 2) {
+  // ---- finished column j-1 (publisher): r1_prev + t - H[0:j, 0:j-1] (t_prev / gamma_prev)
+  if (pub && gs == 2) {
     hess_matvec<STAGED>(Hs, sx, sr1, j);   // sr1 is free until the first sweep below
     __syncthreads();
     for (int i = tid; i < j; i += blockDim.x) shc[i] = shc[i] + st[i] - sr1[i];
@@ -741,105 +793,101 @@ __device__ void small_solve(const Work& w, long long n, int j, bool tail, const 
   }
   __syncthreads();
   if (s_flag) {
-    // Cancellation in u^T u - p^T p: store the column without its subdiagonal
-    // and let the update kernel form w = u - V t and its explicit norm.
-    double* hc = w.H + hess_col(j - 1);
-    for (int i = tid; i < j; i += blockDim.x) {
-      hc[i] = shc[i];
-      w.coef_t[i] = st[i];
+    // Cancellation in u^T u - p^T p: every block forms w = u - V t and its
+    // explicit norm; the publisher leaves the column without its subdiagonal.
+    if (pub) {
+      double* hc = w.H + hess_col(j - 1);
+      for (int i = tid; i < j; i += blockDim.x) hc[i] = shc[i];
+      if (tid == 0) {
+        ctl->mode = kUpdFallback;
+        ctl->mode_iter = j;
+      }
     }
-    if (tid == 0) {
-      ctl->mode = kUpdFallback;
-      ctl->mode_iter = j;
-    }
-    return;
+    out.mode = kUpdFallback;
+    return out;
   }
   const double gamma = s_gamma;
   const double ig = 1.0 / gamma;
+  out.ig = ig;
 
-  // ---- Hessenberg column, Givens rotation, breakdown test --------------------
-  const int brk = finish_column(w, j, shc, gamma, scs, ssn, s_gc, n);
-  if (brk) {
-    if (tid == 0) {
-      ctl->status = kBreakdown;
-      ctl->J = j;
-      ctl->active = 0;
-      ctl->breakdowns += 1;
-    }
-    return;
-  }
-
-  // ---- new row of L (p / gamma) and of T = (I + L)^{-1} (eq:block) ---------
+  // ---- new row of L (p / gamma) ---------------------------------------------
   for (int c = tid; c < j; c += blockDim.x) {
     const double l = P[c] * ig;
     sl[c] = l;
-    w.L[(size_t)c * w.ldt + j] = l;
-  }
-  __syncthreads();
-  tri_rowvec<STAGED>(Ts, sl, sx, j);
-  __syncthreads();
-  {
-    double* trow = w.T + tri_row(j);
-    for (int c = tid; c < j; c += blockDim.x) trow[c] = sx[c];
-    if (tid == 0) trow[j] = 1.0;
+    if (pub) w.L[(size_t)c * w.ldt + j] = l;
   }
 
-  // ---- stopping tests ----------------------------------------------------------
-  if (tid == 0) {
-    int st_code = kRunning;
-    if (ctl->gabs <= ctl->tol_abs) st_code = kConverged;
-    else if (j >= m) st_code = kFull;
-    else if (ctl->its_before + j >= ctl->maxit) st_code = kMaxit;
-    s_flag = st_code;
-  }
-  __syncthreads();
-  if (s_flag != kRunning) {
-    for (int i = tid; i < j; i += blockDim.x) w.coef_t[i] = st[i];
+  // ---- publisher: Hessenberg column, Givens rotation, breakdown test, the row
+  // of T = (I + L)^{-1} (eq:block), stopping tests
+  int st_code = kRunning;
+  if (pub) {
+    const int brk = finish_column(w, j, shc, gamma, scs, ssn, s_gc, n);   // synchronises
+    if (!brk) {
+      tri_rowvec<STAGED>(Ts, sl, sx, j);
+      __syncthreads();
+      double* trow = w.T + tri_row(j);
+      for (int c = tid; c < j; c += blockDim.x) trow[c] = sx[c];
+      if (tid == 0) trow[j] = 1.0;
+    }
     if (tid == 0) {
-      ctl->status = s_flag;
-      ctl->J = j;
-      ctl->active = 0;
-      ctl->inv_gamma = ig;
-      ctl->mode = ctl->final_v ? kUpdVOnly : kUpdNone;
+      int code = kRunning;
+      if (brk) code = kBreakdown;
+      else if (ctl->gabs <= ctl->tol_abs) code = kConverged;
+      else if (j >= m) code = kFull;
+      else if (ctl->its_before + j >= ctl->maxit) code = kMaxit;
+      s_flag = code;
+      if (code != kRunning) {
+        ctl->status = code;
+        ctl->J = j;
+        ctl->end_iter = j;
+        if (brk) ctl->breakdowns += 1;
+      }
+    }
+    __syncthreads();
+    st_code = s_flag;
+  }
+
+  // ---- first sweep of the next vector (all blocks; none at the tail) --------
+  if (!tail) {
+    if (gs == 2) {
+      // Stephen's trick: r1 = [q/gamma ; beta/gamma^2 - (t/gamma)^T (q/gamma)]
+      for (int c = tid; c < j; c += blockDim.x) {
+        sr1[c] = Q[c] * ig;
+        sx[c] = st[c] * ig;
+      }
+      __syncthreads();
+      if (wave == 0) {
+        const double d = wave_dot(sx, sr1, j);
+        if (lane == 0) sr1[j] = beta * ig * ig - d;
+      }
+    } else {
+      // r1 = (I + L_{0:j+1,0:j+1})^{-1} [q/gamma ; beta/gamma^2]
+      for (int c = tid; c < j; c += blockDim.x) sx[c] = Q[c] * ig;
+      __syncthreads();
+      tri_matvec<STAGED>(Ts, sx, sr1, j);
+      __syncthreads();
+      if (wave == 0) {
+        const double d = wave_dot(sl, sr1, j);
+        if (lane == 0) sr1[j] = beta * ig * ig - d;
+      }
+    }
+    __syncthreads();
+  }
+  if (pub) {
+    if (st_code == kRunning) {
+      for (int i = tid; i <= j; i += blockDim.x) {
+        w.coef_r1[i] = sr1[i];
+        if (i < j) w.coef_t[i] = st[i];
+      }
+    }
+    if (tid == 0) {
+      if (st_code == kRunning) ctl->gamma_prev = gamma;
+      ctl->mode = run_mode;
       ctl->mode_iter = j;
     }
-    return;
   }
-
-  // ---- first sweep of the next vector ----------------------------------------
-  if (gs == 2) {
-    // Stephen's trick: r1 = [q/gamma ; beta/gamma^2 - (t/gamma)^T (q/gamma)]
-    for (int c = tid; c < j; c += blockDim.x) {
-      sr1[c] = Q[c] * ig;
-      sx[c] = st[c] * ig;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const double d = wave_dot(sx, sr1, j);
-      if (lane == 0) sr1[j] = beta * ig * ig - d;
-    }
-  } else {
-    // r1 = (I + L_{0:j+1,0:j+1})^{-1} [q/gamma ; beta/gamma^2]
-    for (int c = tid; c < j; c += blockDim.x) sx[c] = Q[c] * ig;
-    __syncthreads();
-    tri_matvec<STAGED>(Ts, sx, sr1, j);
-    __syncthreads();
-    if (wave == 0) {
-      const double d = wave_dot(sl, sr1, j);
-      if (lane == 0) sr1[j] = beta * ig * ig - d;
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i <= j; i += blockDim.x) {
-    w.coef_r1[i] = sr1[i];
-    if (i < j) w.coef_t[i] = st[i];
-  }
-  if (tid == 0) {
-    ctl->inv_gamma = ig;
-    ctl->gamma_prev = gamma;
-    ctl->mode = kUpdNormal;
-    ctl->mode_iter = j;
-  }
+  out.mode = run_mode;
+  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -1034,7 +1082,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
     double* __restrict__ raw_out) {
   extern __shared__ double lds[];
   const bool raw = (raw_out != nullptr);
-  if (!raw && !ctl_active(w.ctl)) return;
+  if (!raw && !ctl_runs(w.ctl, j)) return;
   const double* __restrict__ V = raw ? Vraw : w.V;
   const long long ldv = raw ? ldv_raw : w.ldv;
   const double* __restrict__ z = raw ? zraw : w.z;
@@ -1078,27 +1126,24 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
       part[v] = acc;
     }
   }
-  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol))
-    return;
-  if (raw) {
-    for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) raw_out[v] = lds[v];
+  if (!raw) {
+    // The group totals stay in w.gpart: every block of this iteration's
+    // update kernel sums them and runs the small solve itself.
+    group_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol);
     return;
   }
-  if (stage_count(j) > 0)
-    small_solve<true>(w, n, j, !Z, lds, lds + ncol, lds + 2 * ncol);
-  else
-    small_solve<false>(w, n, j, !Z, lds, lds + ncol, lds + 2 * ncol);
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol))
+    return;
+  for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) raw_out[v] = lds[v];
 }
 
 // Shared memory of the fused reduction: the wave partials; then the totals
-// (2 ncol) followed by either the grid-reduction scratch or the small solve.
+// (2 ncol) followed by the grid-reduction scratch.
 static size_t reduce_lds_bytes(const ReduceShape& s, int ncol) {
   const size_t nv = (size_t)2 * ncol;
-  size_t a = (size_t)s.wr * nv;
-  size_t b = nv + (nv > (size_t)kReduceThreads ? nv : (size_t)kReduceThreads);
-  size_t c = nv + 7 * (size_t)(ncol + 2) + stage_count(ncol - 1);
-  size_t m = a > b ? a : b;
-  return (m > c ? m : c) * sizeof(double);
+  const size_t a = (size_t)s.wr * nv;
+  const size_t b = nv + (nv > (size_t)kReduceThreads ? nv : (size_t)kReduceThreads);
+  return (a > b ? a : b) * sizeof(double);
 }
 
 // Blocks of `kernel` that are resident at once on the current device with
@@ -1193,36 +1238,62 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
 // Basis update: one pass over V_{0:j}
 // ---------------------------------------------------------------------------
 
+// Shared memory of the update kernel for iteration j: the reduction totals
+// (2 (j+1)), the small-solve scratch (7 (j+2)) and the staged T and H.
+__host__ __device__ __forceinline__ size_t update_lds_doubles(int j) {
+  return (size_t)2 * (j + 1) + (size_t)7 * (j + 2) + stage_count(j);
+}
+
 template <bool HAS_T, bool VEC>
 __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
-    Work w, long long n, int j, double* __restrict__ Vraw, long long ldv_raw,
+    Work w, long long n, int j, int ngroups, double* __restrict__ Vraw, long long ldv_raw,
     const double* __restrict__ zraw, const double* __restrict__ traw,
     const double* __restrict__ r1raw, double igraw, int raw) {
+  extern __shared__ double sdyn[];
+  double* sP = sdyn;                 // V_{0:j}^T u and u^T u
+  double* sQ = sdyn + (j + 1);       // V_{0:j}^T z and u^T z
+  double* sm = sdyn + 2 * (j + 1);   // small-solve scratch; t at sm, r1 at sm + 2 (j+2)
+  const double* t = sm;
+  const double* r1 = sm + 2 * (j + 2);
   int mode;
   double ig;
   double* __restrict__ V;
   long long ldv;
   const double* __restrict__ z;
-  const double* __restrict__ t;
-  const double* __restrict__ r1;
   if (raw) {
     mode = kUpdNormal;
     ig = igraw;
     V = Vraw;
     ldv = ldv_raw;
     z = zraw;
-    t = traw;
-    r1 = r1raw;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+      if (i < j) sm[i] = traw[i];
+      sm[2 * (j + 2) + i] = r1raw[i];
+    }
+    __syncthreads();
   } else {
-    if (load_agent(&w.ctl->mode_iter) != j) return;
-    mode = load_agent(&w.ctl->mode);
-    if (mode == kUpdNone) return;
-    ig = w.ctl->inv_gamma;
+    if (!ctl_runs(w.ctl, j)) return;
     V = w.V;
     ldv = w.ldv;
     z = w.z;
-    t = w.coef_t;
-    r1 = w.coef_r1;
+    // the reduction totals: the group rows it left, summed in a fixed order
+    for (int v = threadIdx.x; v < 2 * (j + 1); v += blockDim.x) {
+      double g8[8];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) g8[g] = (g < ngroups) ? w.gpart[(size_t)g * w.pstride + v] : 0.0;
+      double acc = g8[0];
+#pragma unroll
+      for (int g = 1; g < 8; ++g) acc += g8[g];
+      sdyn[v] = acc;
+    }
+    __syncthreads();
+    const bool tail = (j >= w.ctl->m);
+    const bool pub = (blockIdx.x == 0);
+    const StepCoefs c = (stage_count(j) > 0) ? small_solve<true>(w, n, j, tail, sP, sQ, sm, pub)
+                                             : small_solve<false>(w, n, j, tail, sP, sQ, sm, pub);
+    mode = c.mode;
+    ig = c.ig;
+    if (mode == kUpdNone) return;
   }
   const bool need_r = (mode == kUpdNormal);
   const bool fallback = (mode == kUpdFallback);
@@ -1373,7 +1444,9 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   }
   if (!fallback) return;
   // Lagged norm cancelled: w = u - V t is stored unnormalised; its explicit
-  // norm comes from a grid reduction and finishes column j-1.
+  // norm comes from a grid reduction (group totals in rows 8.. of gpart, so
+  // that the reduction totals in rows 0..7 stay intact for blocks that start
+  // later) and finishes column j-1 in the last block.
   __shared__ double red[kUpdateThreads / kWave];
   __shared__ double tot[1];
   __shared__ double scr[kUpdateThreads];
@@ -1385,13 +1458,14 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     for (int k = 0; k < kUpdateThreads / kWave; ++k) acc += red[k];
     w.part[(size_t)blockIdx.x * w.pstride] = acc;
   }
-  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 1, tot, scr)) return;
+  if (!grid_reduce_last(w.part, w.gpart + (size_t)8 * w.pstride, w.pstride, w.tickets, 1, tot, scr))
+    return;
   const double gamma = sqrt(tot[0]);
-  // the group totals are consumed: reuse that global buffer as scratch
-  double* scratch = w.gpart;
-  double* hcol = scratch;
-  double* fcs = scratch + (j + 2);
-  double* fsn = fcs + (j + 2);
+  // scratch in shared memory: the column (as the publisher stored it), the
+  // rotations and g[j-1]
+  double* hcol = sm + (j + 2);
+  double* fcs = sm + 5 * (j + 2);
+  double* fsn = sm + 6 * (j + 2);
   __shared__ double s_gc;
   for (int i = threadIdx.x; i < j; i += blockDim.x) {
     hcol[i] = w.H[hess_col(j - 1) + i];
@@ -1406,7 +1480,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   if (threadIdx.x == 0) {
     Ctl* c = w.ctl;
     c->J = j;
-    c->active = 0;
+    c->end_iter = j;
     c->fallbacks += 1;
     if (brk) {
       c->status = kBreakdown;
@@ -1418,38 +1492,51 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   }
 }
 
-// Tiles of kUpdateThreads * kUpdateRows rows; the grid is capped so that the
-// per-block partials of the fallback path fit the partial-sum buffer.
-static unsigned update_grid(long long n) {
+// Tiles of kUpdateThreads * kUpdateRows rows, one round of resident blocks
+// striding over them (so that every block runs the small solve once), capped
+// so that the per-block partials of the fallback path fit their buffer.
+static unsigned update_grid(const void* kernel, long long n, size_t lds) {
   const long long per = (long long)kUpdateThreads * kUpdateRows;
   long long g = (n + per - 1) / per;
-  if (g > kMaxBlocks) g = kMaxBlocks;
+  long long cap = resident_blocks(kernel, kUpdateThreads, lds);
+  if (cap > kMaxBlocks) cap = kMaxBlocks;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
   return (unsigned)g;
 }
 
-hipError_t launch_update(const Work& w, long long n, int j, int gs, hipStream_t s) {
+typedef void (*UpdateKernel)(Work, long long, int, int, double*, long long, const double*,
+                             const double*, const double*, double, int);
+
+static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t, bool vec,
+                                  int ngroups, double* Vraw, long long ldv_raw,
+                                  const double* zraw, const double* traw, const double* r1raw,
+                                  double igraw, int raw, hipStream_t s) {
+  UpdateKernel k = has_t ? (vec ? update_kernel<true, true> : update_kernel<true, false>)
+                         : (vec ? update_kernel<false, true> : update_kernel<false, false>);
+  const size_t lds = update_lds_doubles(j) * sizeof(double);
+  const unsigned grid = update_grid(reinterpret_cast<const void*>(k), n, lds);
+  Work wa = w;
+  long long na = n, ldva = ldv_raw;
+  int ja = j, nga = ngroups, rawa = raw;
+  double* va = Vraw;
+  const double* za = zraw;
+  const double* ta = traw;
+  const double* ra = r1raw;
+  double iga = igraw;
+  void* args[] = {&wa, &na, &ja, &nga, &va, &ldva, &za, &ta, &ra, &iga, &rawa};
+  return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(kUpdateThreads), args,
+                         lds, s);
+}
+
+hipError_t launch_update(const Work& w, long long n, int j, int gs, int ngroups, hipStream_t s) {
   // With one Gauss-Seidel sweep there is no second-sweep vector t, and the
   // kernel variant without it skips one FMA stream.  16-byte accesses need
   // an even leading dimension and 16-byte aligned columns.
   const bool vec = (w.ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(w.V) % 16 == 0) &&
                    (reinterpret_cast<uintptr_t>(w.z) % 16 == 0);
-  const dim3 g(update_grid(n)), b(kUpdateThreads);
-  if (gs == 2) {
-    if (vec)
-      hipLaunchKernelGGL((update_kernel<true, true>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
-                         nullptr, nullptr, 0.0, 0);
-    else
-      hipLaunchKernelGGL((update_kernel<true, false>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
-                         nullptr, nullptr, 0.0, 0);
-  } else {
-    if (vec)
-      hipLaunchKernelGGL((update_kernel<false, true>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
-                         nullptr, nullptr, 0.0, 0);
-    else
-      hipLaunchKernelGGL((update_kernel<false, false>), g, b, 0, s, w, n, j, nullptr, 0LL, nullptr,
-                         nullptr, nullptr, 0.0, 0);
-  }
-  return hipGetLastError();
+  return update_dispatch(w, n, j, gs == 2, vec, ngroups, nullptr, 0, nullptr, nullptr, nullptr,
+                         0.0, 0, s);
 }
 
 hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
@@ -1457,13 +1544,7 @@ hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const
   Work w{};
   const bool vec = (ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(V) % 16 == 0) &&
                    (reinterpret_cast<uintptr_t>(z) % 16 == 0);
-  if (vec)
-    hipLaunchKernelGGL((update_kernel<true, true>), dim3(update_grid(n)), dim3(kUpdateThreads), 0,
-                       s, w, n, j, V, ldv, z, t, r1, inv_gamma, 1);
-  else
-    hipLaunchKernelGGL((update_kernel<true, false>), dim3(update_grid(n)), dim3(kUpdateThreads), 0,
-                       s, w, n, j, V, ldv, z, t, r1, inv_gamma, 1);
-  return hipGetLastError();
+  return update_dispatch(w, n, j, true, vec, 0, V, ldv, z, t, r1, inv_gamma, 1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1566,7 +1647,10 @@ __global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long lo
 }
 
 hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s) {
-  hipLaunchKernelGGL(xupdate_kernel, dim3(update_grid(n)), dim3(kUpdateThreads), 0, s, w, n, x);
+  const long long per = (long long)kUpdateThreads * kUpdateRows;
+  long long g = (n + per - 1) / per;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  hipLaunchKernelGGL(xupdate_kernel, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w, n, x);
   return hipGetLastError();
 }
 

@@ -234,23 +234,22 @@ struct Timed {
   }
 };
 
-// Did launch (kernel, j) of a cycle that ended after iteration j_end with
-// update mode `mode_end` do work?
-bool launch_ran(int kernel, int j, int j_end, int m, bool update_at_end) {
+// Did launch (kernel, j) of a cycle that ended at iteration j_end do work?
+bool launch_ran(int kernel, int j, int j_end, int m) {
   switch (kernel) {
     case IGS_K_SPMV: return j <= j_end && j < m;
     case IGS_K_REDUCE: return j <= j_end;
-    case IGS_K_UPDATE: return j < j_end || (j == j_end && update_at_end);
+    case IGS_K_UPDATE: return j <= j_end;
     default: return true;
   }
 }
 
 // At the end of a cycle: record which of its launches did work.  The event
 // times themselves are read later (harvest), outside any timed loop.
-void mark_cycle(igs_ctx* c, int j_end, int m, bool update_at_end, int J, double dn) {
+void mark_cycle(igs_ctx* c, int j_end, int m, int J, double dn) {
   for (EventPair& p : c->pending) {
     if (p.ran >= 0) continue;  // launches of earlier cycles are already marked
-    bool ran = launch_ran(p.kernel, p.j, j_end, m, update_at_end);
+    bool ran = launch_ran(p.kernel, p.j, j_end, m);
     if (p.kernel == IGS_K_XUPDATE) {
       ran = J > 0;
       p.bytes = 8.0 * dn * J + 16.0 * dn;
@@ -507,7 +506,6 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   double relres = NAN, arn = NAN;
   bool converged = false;
   bool final_check = false;
-  int fallbacks_seen = 0;
   while (true) {
     const long long its_before = its;
     const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
@@ -516,24 +514,27 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w.V, w, its_before, maxit_cycle, m,
                                           gs_iters, final_v, tol, tau, s));
     }
+    // A check cycle (after the iteration budget) runs iteration 0 only: the
+    // residual norm decides between convergence and giving up.
     const int jmax = final_check ? 0 : m;
     for (int j = 0; j <= jmax; ++j) {
       const double* u = w.V + (size_t)j * w.ldv;
       if (j < m) {
         Timed tm(c, pmask, IGS_K_SPMV, j, cycles, op_bytes);
-        HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, w.z, w.ctl, s));
+        HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, w.z, w.ctl, j, s));
       }
+      int nb = 0;
       {
         Timed tm(c, pmask, IGS_K_REDUCE, j, cycles, 8.0 * dn * (j + 1) + (j < m ? 8.0 * dn : 0.0));
-        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, s, nullptr));
+        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, s, &nb));
       }
-      if (final_check) break;
-      // The tail update (j = m) is queued too: it finishes the last column
-      // when the lagged norm cancelled there, or writes v_m on request, and
-      // returns at once otherwise.  It never writes column m + 1.
+      // The update kernel runs the small solve of iteration j in every block.
+      // The tail update (j = m) finishes the last column (and the lagged-norm
+      // fallback there) and writes v_m on request; it never writes column
+      // m + 1.
       {
         Timed tm(c, pmask, IGS_K_UPDATE, j, cycles, 8.0 * dn * (j + 1) + 8.0 * dn + 16.0 * dn);
-        HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_iters, s));
+        HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_iters, igs::reduce_groups(nb), s));
       }
     }
     if (!final_check) {
@@ -548,13 +549,10 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     status = h.status;
     const int J = h.J;
     if (prof) {
-      int j_end = J;
-      if (status == igs::kNonfinite) j_end = J + 1;
-      const bool fell_back = h.fallbacks > fallbacks_seen;
-      const bool upd_end = (h.mode_iter == j_end) && (h.mode == igs::kUpdVOnly || fell_back);
-      mark_cycle(c, j_end, m, upd_end, final_check ? 0 : J, dn);
+      // the iteration at which the cycle ended (every cycle ends by its tail)
+      const int j_end = (h.end_iter == igs::kNotEnded) ? m : h.end_iter;
+      mark_cycle(c, j_end, m, final_check ? 0 : J, dn);
     }
-    fallbacks_seen = h.fallbacks;
     if (cycles == 0 && !final_check) {
       c->J_first = J;
       c->ldh_first = w.ldh;
@@ -654,7 +652,7 @@ extern "C" int igs_debug_copy_V(igs_ctx* c, double* V_dev, int64_t ldv, int* nco
 extern "C" int igs_kernel_spmv(igs_ctx* c, const double* u, double* z) {
   if (!c || !u || !z) return IGS_EINVAL;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, z, nullptr, c->stream));
+  HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, z, nullptr, 0, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   return IGS_OK;
 }
