@@ -198,11 +198,13 @@ __device__ __forceinline__ double wave_dot(const double* a, const double* b, int
 // operator apply: z = A u  (or r = b - A x)
 // ---------------------------------------------------------------------------
 
-// CSR with LPR lanes per row and RPG consecutive rows per lane group.  The
-// lanes of a row read its entries as one contiguous, coalesced segment; the
-// row bounds, the first LPR entries of every row of the group and the x
-// gathers are each issued as one batch, so a group pays about three memory
-// latencies for RPG rows.  Rows longer than LPR finish in a strided loop.
+// CSR with LPR lanes per row.  A wave holds G = 64 / LPR lane groups and
+// covers G * RPG consecutive rows: group g takes rows base + q G + g,
+// q < RPG, so that for each q the wave's loads of row bounds, entries and x
+// gathers cover G consecutive rows (contiguous for the entries).  The row
+// bounds, the first LPR entries of every row and the x gathers are each
+// issued as one batch, so a group pays about three memory latencies for RPG
+// rows.  Rows longer than LPR finish in a strided loop.
 template <int LPR, int RPG>
 __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* __restrict__ rp,
                                                        const int* __restrict__ ci,
@@ -211,24 +213,30 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
                                                        double* __restrict__ y,
                                                        const double* __restrict__ bsub,
                                                        const Ctl* __restrict__ gate, int gate_j) {
+  constexpr int G = kWave / LPR;
   // the gate is read together with the row bounds, so its latency overlaps
   // theirs; nothing is stored before it is checked
   const int act = (gate != nullptr) ? (load_agent(&gate->end_iter) >= gate_j) : 1;
   const long long lb = xcd_block(blockIdx.x, gridDim.x);
-  const long long grp = (lb * blockDim.x + threadIdx.x) / LPR;
+  const long long wv = (lb * blockDim.x + threadIdx.x) / kWave;
+  const int g = (int)(threadIdx.x % kWave) / LPR;
   const int lane = threadIdx.x % LPR;
-  const long long row0 = grp * RPG;
-  if (row0 >= n) return;  // the LPR lanes of a group leave together
-  int bnd[RPG + 1];
+  const long long base = wv * (long long)(G * RPG);
+  if (base + g >= n) return;  // the group's first row is past the end: its lanes leave together
+  int bs[RPG], be[RPG];
 #pragma unroll
-  for (int q = 0; q <= RPG; ++q) bnd[q] = rp[min(row0 + q, n)];
+  for (int q = 0; q < RPG; ++q) {
+    const long long row = base + (long long)q * G + g;
+    bs[q] = rp[min(row, n)];
+    be[q] = rp[min(row + 1, n)];
+  }
   if (!act) return;
   int cidx[RPG];
   double val[RPG];
 #pragma unroll
   for (int q = 0; q < RPG; ++q) {
-    const int k = bnd[q] + lane;
-    const bool ok = k < bnd[q + 1];
+    const int k = bs[q] + lane;
+    const bool ok = k < be[q];
     cidx[q] = ok ? ci[k] : 0;
     val[q] = ok ? va[k] : 0.0;
   }
@@ -237,7 +245,7 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
   for (int q = 0; q < RPG; ++q) acc[q] = val[q] * x[cidx[q]];
 #pragma unroll
   for (int q = 0; q < RPG; ++q)
-    for (int k = bnd[q] + lane + LPR; k < bnd[q + 1]; k += LPR) acc[q] = fma(va[k], x[ci[k]], acc[q]);
+    for (int k = bs[q] + lane + LPR; k < be[q]; k += LPR) acc[q] = fma(va[k], x[ci[k]], acc[q]);
 #pragma unroll
   for (int q = 0; q < RPG; ++q) {
     if constexpr (LPR <= 16) {
@@ -247,22 +255,12 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
       for (int off = LPR / 2; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, LPR);
     }
   }
-  if constexpr (LPR >= RPG) {
-    // lane q of the group stores row q: one coalesced store per wave
-    if (lane < RPG) {
-      double out = acc[0];
+  // lane l of a group stores the rows q with q % LPR == l; for each q the
+  // wave's stores cover G consecutive rows
 #pragma unroll
-      for (int q = 1; q < RPG; ++q) out = (lane == q) ? acc[q] : out;
-      const long long row = row0 + lane;
-      if (row < n) y[row] = (bsub != nullptr) ? bsub[row] - out : out;
-    }
-  } else {
-    // fewer lanes than rows: lane l stores rows q = l, l + LPR, ...
-#pragma unroll
-    for (int q = 0; q < RPG; ++q) {
-      const long long row = row0 + q;
-      if (q % LPR == lane && row < n) y[row] = (bsub != nullptr) ? bsub[row] - acc[q] : acc[q];
-    }
+  for (int q = 0; q < RPG; ++q) {
+    const long long row = base + (long long)q * G + g;
+    if (q % LPR == lane && row < n) y[row] = (bsub != nullptr) ? bsub[row] - acc[q] : acc[q];
   }
 }
 
