@@ -1145,7 +1145,8 @@ static size_t reduce_lds_bytes(const ReduceShape& s, int ncol) {
 }
 
 // Blocks of `kernel` that are resident at once on the current device with
-// `threads` threads and `lds` bytes of dynamic shared memory (cached).
+// `threads` threads and `lds` bytes of dynamic shared memory (cached); with
+// kernel == nullptr, the number of compute units.
 static int resident_blocks(const void* kernel, int threads, size_t lds) {
   static std::mutex mu;
   static std::map<std::tuple<int, const void*, int, size_t>, int> cache;
@@ -1159,8 +1160,10 @@ static int resident_blocks(const void* kernel, int threads, size_t lds) {
   if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus < 1)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess ||
-      per < 1)
+  // kernel == nullptr: the number of CUs
+  if (kernel == nullptr) per = 1;
+  else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess ||
+           per < 1)
     per = 1;
   const int r = cus * per;
   cache[key] = r;
@@ -1203,6 +1206,12 @@ static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z
   int cap = resident_blocks(reinterpret_cast<const void*>(pick_reduce(sh.tcpw, vec, true)),
                             kReduceThreads, lds);
   if (cap > kMaxBlocks) cap = kMaxBlocks;
+  // with one or two columns a block streams little: one block per CU keeps
+  // the fixed per-block costs (partials, arrival counters) small
+  if (sh.tcpw <= 2) {
+    const int cus = resident_blocks(nullptr, 0, 0);
+    if (cap > cus) cap = cus;
+  }
   reduce_rows(sh, n, cap);
   if (nblocks_out) *nblocks_out = sh.nblocks;
   Work wa = w;
@@ -1495,10 +1504,13 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
 // so that the per-block partials of the fallback path fit their buffer.
 static unsigned update_grid(const void* kernel, long long n, size_t lds) {
   const long long per = (long long)kUpdateThreads * kUpdateRows;
-  long long g = (n + per - 1) / per;
+  const long long tiles = (n + per - 1) / per;
   long long cap = resident_blocks(kernel, kUpdateThreads, lds);
   if (cap > kMaxBlocks) cap = kMaxBlocks;
-  if (g > cap) g = cap;
+  if (cap < 1) cap = 1;
+  // every block strides over the same number of tiles (no half-empty round)
+  const long long rounds = (tiles + cap - 1) / cap;
+  long long g = (tiles + rounds - 1) / rounds;
   if (g < 1) g = 1;
   return (unsigned)g;
 }
