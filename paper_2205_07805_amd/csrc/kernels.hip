@@ -4,11 +4,13 @@
 // finishes Hessenberg column j-1) the host queues three kernels:
 //
 //   spmv     z = A u_j                              (operator apply; skipped at j = m)
-//   reduce   [V_{0:j}, u_j]^T [u_j, z]              (the ONE global reduction)
-//            + in the last block to arrive: the small solve (lagged norm,
-//              second Gauss-Seidel sweep, Stephen's trick, Hessenberg column,
-//              Givens rotation, stopping tests)
-//   update   v_j = (u_j - V t) / gamma,
+//   reduce   [V_{0:j}, u_j]^T [u_j, z]              (the ONE global reduction;
+//                                                     it ends with 8 group totals)
+//   update   in every block: the totals, then the small solve (lagged norm,
+//              second Gauss-Seidel sweep, Stephen's trick; block 0 also the
+//              Hessenberg column, Givens rotation, rows of L and T, stopping
+//              tests), then its share of
+//            v_j = (u_j - V t) / gamma,
 //            u_{j+1} = z / gamma - V r1 - v_j r1_j     (one pass over V)
 //
 // u_j lives in column j of V until the update overwrites it with v_j.  All
@@ -889,7 +891,7 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
 }
 
 // ---------------------------------------------------------------------------
-// Fused reduction [V_{0:j}, u]^T [u, z] (+ small solve in the last block)
+// Fused reduction [V_{0:j}, u]^T [u, z]
 // ---------------------------------------------------------------------------
 //
 // A block owns a contiguous row range.  Its 8 waves are arranged as Wc column
