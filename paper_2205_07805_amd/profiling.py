@@ -38,9 +38,18 @@ KERNEL_SRC = os.path.join(HERE, "csrc", "kernels.hip")
 NOOP_US = 4.0
 
 
+def code_sha(text: str) -> str:
+    """Hash of C++ source with comments and whitespace removed: edits to
+    comments do not change it, edits to code do."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = re.sub(r"\s+", " ", text).strip()
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
 def kernel_source_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(KERNEL_SRC, encoding="utf-8") as f:
+        return code_sha(f.read())
 
 
 def short_name(name: str) -> str:
