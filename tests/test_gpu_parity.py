@@ -240,3 +240,21 @@ def test_invalid_input_errors(torch):
     with pytest.raises(igs.IgsError):
         bad = W.Csr(3, np.array([0, 2, 1, 3], np.int32), np.array([0, 1, 2], np.int32), np.ones(3))
         Solver(bad)
+
+
+def test_dense_nonnormal_4096_full_gmres_200(torch):
+    """Dense non-normal n = 4096, one full GMRES(200) cycle (tol 0): the
+    dense operator path and the small solve from device memory (j > 78)."""
+    a, b = W.make_dense_nonnormal(4096)
+    print("dense non-normal n=4096 m=200", flush=True)
+    x, rc, info, H, V = gpu(a, b, 200, 0.0, 2, max_cycles=1, keep_first_basis=1,
+                            final_basis_vector=1)
+    ref = O.gmres(a, b, restart=200, tol=0.0, variant="igs1r", max_cycles=1).first_cycle
+    J = info["first_cycle_J"]
+    assert J == ref.J == 200
+    op = O.as_operator(a)
+    anorm = D.norm2_estimate(op, 4096, iters=100)   # a lower bound: conservative
+    loss_ref = D.orthogonality_loss(ref.V[:, : J + 1])
+    assert D.orthogonality_loss(V[:, : J + 1]) <= max(1e-13, 10 * loss_ref)
+    assert D.arnoldi_relation_residual(op, V[:, : J + 1], H, anorm) < 1e-13
+    assert_H_close(H, ref.H, ncols=10, tol=1e-11)
