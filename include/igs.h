@@ -81,7 +81,19 @@ typedef struct igs_opts {
                            igs_debug_copy_V (costs one copy of the basis)      */
   int profile_kernels;  /* with profile = 1: bit (1 << IGS_K_*) selects the
                            kernels to time; 0 means all                        */
-  int reserved[5];
+  int inner_fp32;       /* 1: mixed precision (the paper's Conclusions name it
+                           as future work).  Each restart cycle runs in FP32
+                           (operator apply with FP32 values, the fused
+                           reduction with FP64 sums, the basis update with FP64
+                           coefficients), while the residual b - A x, the
+                           small solve, the Givens least squares and
+                           x = x0 + V y stay in FP64: iterative refinement with
+                           one FP32 Arnoldi cycle per correction.  CSR
+                           operators only (IGS_ENOTIMPL otherwise).            */
+  int reserved[2];
+  double inner_rtol;    /* inner_fp32: a cycle also ends once its Arnoldi
+                           residual is <= inner_rtol * ||r0|| of the cycle;
+                           <= 0 means 1e-5                                     */
 } igs_opts;
 
 /* Result summary of a solve.  Any pointer argument of this type may be NULL. */

@@ -58,6 +58,8 @@ struct Ctl {
   double rho;          // ||r0|| of the cycle
   double gabs;         // |g_J| after the last finished column
   double gamma_prev;   // gamma of the previous iteration
+  double cycle_rtol;   // > 0: a cycle also ends once |g_j| <= cycle_rtol * rho
+  double tol_cyc;      // the Arnoldi-residual target of the current cycle
   int nonfinite_in;    // count of non-finite entries in b and x0
   int pad;
 };
@@ -72,6 +74,7 @@ struct Op {
   const double* A;     // dense
   long long lda;
   int lpr;             // CSR lanes per row
+  const float* vals32; // CSR values rounded to FP32 (mixed precision; may be null)
 };
 
 // Device workspace of a context (all device pointers).
@@ -91,6 +94,9 @@ struct Work {
   int pstride;
   unsigned* tickets;             // [kMaxGroups + 1] arrival counters
   Ctl* ctl;
+  float* V32;                    // FP32 basis (mixed precision), same ldv
+  float* z32;                    // FP32 A u
+  int fp32;                      // 1: the step kernels work on V32 / z32
 };
 
 // Groups of the first level of the deterministic grid reduction for a grid
@@ -102,9 +108,14 @@ __host__ __device__ inline int reduce_groups(int nb) { return nb < 8 ? nb : 8; }
 // gate: skip when the cycle ended before iteration j (nullptr: always run).
 hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, int j,
                        hipStream_t s);
-hipError_t launch_residual(const Op& op, const double* b, const double* x, double* r,
-                           const Work& w, long long its_before, long long maxit, int m,
-                           int gs, int final_v, double tol, double tau, hipStream_t s);
+// Cycle start: reset the control block, then r = b - A x (FP64) into column 0
+// of the basis (V, or V32 rounded to FP32 when w.fp32).
+hipError_t launch_residual(const Op& op, const double* b, const double* x, const Work& w,
+                           long long its_before, long long maxit, int m, int gs, int final_v,
+                           double tol, double tau, double cycle_rtol, hipStream_t s);
+hipError_t launch_spmv32(const Op& op, const float* u, float* z, const Ctl* gate, int j,
+                         hipStream_t s);
+hipError_t launch_round_to_float(const double* src, float* dst, long long count, hipStream_t s);
 hipError_t launch_bnorm(const double* b, const double* x, long long n, const Work& w,
                         hipStream_t s);
 hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,

@@ -23,6 +23,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace igs {
 
@@ -65,6 +66,20 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (G >= 2) v += dpp_move<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_move<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_move<0x141>(v);
+  if constexpr (G >= 16) v += dpp_move<0x140>(v);
+  return v;
+}
+
 // Sum over the 64 lanes of a wave, returned in every lane (a wave-uniform
 // value).  All lanes of the wave must be active.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -81,6 +96,30 @@ __device__ __forceinline__ dvec2 ld_stream2(const double* p) {
   return __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
 }
 __device__ __forceinline__ dvec2 ld2(const double* p) { return *reinterpret_cast<const dvec2*>(p); }
+
+// 16-byte vectors of the basis element type: W consecutive rows per lane
+// (2 doubles or 4 floats).
+template <typename T> struct Vec16;
+template <> struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int W = 2;
+};
+template <> struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int W = 4;
+};
+template <typename T>
+__device__ __forceinline__ typename Vec16<T>::type ld16(const T* p) {
+  return *reinterpret_cast<const typename Vec16<T>::type*>(p);
+}
+template <typename T>
+__device__ __forceinline__ typename Vec16<T>::type ld16_stream(const T* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const typename Vec16<T>::type*>(p));
+}
+template <typename T>
+__device__ __forceinline__ void st16(T* p, const typename Vec16<T>::type& v) {
+  *reinterpret_cast<typename Vec16<T>::type*>(p) = v;
+}
 
 __device__ __forceinline__ int load_agent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -207,13 +246,14 @@ __device__ __forceinline__ double wave_dot(const double* a, const double* b, int
 // bounds, the first LPR entries of every row and the x gathers are each
 // issued as one batch, so a group pays about three memory latencies for RPG
 // rows.  Rows longer than LPR finish in a strided loop.
-template <int LPR, int RPG>
+// TA: type of the matrix values, x, bsub and the sums; TY: type of y.
+template <int LPR, int RPG, typename TA, typename TY>
 __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* __restrict__ rp,
                                                        const int* __restrict__ ci,
-                                                       const double* __restrict__ va,
-                                                       const double* __restrict__ x,
-                                                       double* __restrict__ y,
-                                                       const double* __restrict__ bsub,
+                                                       const TA* __restrict__ va,
+                                                       const TA* __restrict__ x,
+                                                       TY* __restrict__ y,
+                                                       const TA* __restrict__ bsub,
                                                        const Ctl* __restrict__ gate, int gate_j) {
   constexpr int G = kWave / LPR;
   // the gate is read together with the row bounds, so its latency overlaps
@@ -234,15 +274,15 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
   }
   if (!act) return;
   int cidx[RPG];
-  double val[RPG];
+  TA val[RPG];
 #pragma unroll
   for (int q = 0; q < RPG; ++q) {
     const int k = bs[q] + lane;
     const bool ok = k < be[q];
     cidx[q] = ok ? ci[k] : 0;
-    val[q] = ok ? va[k] : 0.0;
+    val[q] = ok ? va[k] : TA(0);
   }
-  double acc[RPG];
+  TA acc[RPG];
 #pragma unroll
   for (int q = 0; q < RPG; ++q) acc[q] = val[q] * x[cidx[q]];
 #pragma unroll
@@ -262,7 +302,7 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
 #pragma unroll
   for (int q = 0; q < RPG; ++q) {
     const long long row = base + (long long)q * G + g;
-    if (q % LPR == lane && row < n) y[row] = (bsub != nullptr) ? bsub[row] - acc[q] : acc[q];
+    if (q % LPR == lane && row < n) y[row] = (TY)((bsub != nullptr) ? bsub[row] - acc[q] : acc[q]);
   }
 }
 
@@ -292,15 +332,26 @@ __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const doub
   if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
 }
 
-static hipError_t op_apply(const Op& op, const double* x, double* y, const double* bsub,
-                           const Ctl* gate, int gate_j, hipStream_t s) {
+template <typename TA> const TA* op_vals(const Op& op);
+template <> const double* op_vals<double>(const Op& op) { return op.vals; }
+template <> const float* op_vals<float>(const Op& op) { return op.vals32; }
+
+template <typename TA, typename TY>
+static hipError_t op_apply(const Op& op, const TA* x, TY* y, const TA* bsub, const Ctl* gate,
+                           int gate_j, hipStream_t s) {
   if (op.dense) {
-    const int rows_per_block = 4;
-    const unsigned grid = (unsigned)((op.n + rows_per_block - 1) / rows_per_block);
-    hipLaunchKernelGGL(gemv_dense_kernel, dim3(grid), dim3(256), 0, s, op.n, op.A, op.lda, x, y,
-                       bsub, gate, gate_j);
-    return hipGetLastError();
+    if constexpr (std::is_same<TA, double>::value && std::is_same<TY, double>::value) {
+      const int rows_per_block = 4;
+      const unsigned grid = (unsigned)((op.n + rows_per_block - 1) / rows_per_block);
+      hipLaunchKernelGGL(gemv_dense_kernel, dim3(grid), dim3(256), 0, s, op.n, op.A, op.lda, x, y,
+                         bsub, gate, gate_j);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;   // the dense operator is FP64 only
+    }
   }
+  const TA* vals = op_vals<TA>(op);
+  if (vals == nullptr) return hipErrorInvalidValue;
   // lanes per row LPR (a power of two near the mean row length), rows per lane
   // group RPG: up to 4 rows while a group is at most 8 lanes wide
   const int lpr = op.lpr;
@@ -312,8 +363,8 @@ static hipError_t op_apply(const Op& op, const double* x, double* y, const doubl
   switch (lpr) {
 #define IGS_SPMV_CASE(L, R)                                                                     \
   case L:                                                                                       \
-    hipLaunchKernelGGL((spmv_csr_kernel<L, R>), dim3(grid), dim3(256), 0, s, op.n, op.row_ptr,  \
-                       op.col_idx, op.vals, x, y, bsub, gate, gate_j);                          \
+    hipLaunchKernelGGL((spmv_csr_kernel<L, R, TA, TY>), dim3(grid), dim3(256), 0, s, op.n,      \
+                       op.row_ptr, op.col_idx, vals, x, y, bsub, gate, gate_j);                 \
     break;
     IGS_SPMV_CASE(1, LPR_RPG_MAX) IGS_SPMV_CASE(2, LPR_RPG_MAX) IGS_SPMV_CASE(4, LPR_RPG_MAX)
     IGS_SPMV_CASE(8, LPR_RPG_MAX) IGS_SPMV_CASE(16, 2) IGS_SPMV_CASE(32, 1) IGS_SPMV_CASE(64, 1)
@@ -325,7 +376,30 @@ static hipError_t op_apply(const Op& op, const double* x, double* y, const doubl
 
 hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, int j,
                        hipStream_t s) {
-  return op_apply(op, u, z, nullptr, gate, j, s);
+  return op_apply<double, double>(op, u, z, nullptr, gate, j, s);
+}
+
+hipError_t launch_spmv32(const Op& op, const float* u, float* z, const Ctl* gate, int j,
+                         hipStream_t s) {
+  return op_apply<float, float>(op, u, z, nullptr, gate, j, s);
+}
+
+// FP64 values of the operator rounded to FP32 (the inner step of the
+// mixed-precision solve).
+__global__ void round_to_float_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                      long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+hipError_t launch_round_to_float(const double* src, float* dst, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  long long blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(round_to_float_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst,
+                     count);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -333,7 +407,7 @@ hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate
 // ---------------------------------------------------------------------------
 
 __global__ void cycle_begin_kernel(Ctl* c, long long its_before, long long maxit, int m, int gs,
-                                   int final_v, double tol, double tau) {
+                                   int final_v, double tol, double tau, double cycle_rtol) {
   if (threadIdx.x != 0) return;
   c->end_iter = kNotEnded;
   c->J = 0;
@@ -347,18 +421,21 @@ __global__ void cycle_begin_kernel(Ctl* c, long long its_before, long long maxit
   c->final_v = final_v;
   c->tol = tol;
   c->tol_abs = tol * c->bnorm;
+  c->tol_cyc = c->tol_abs;
+  c->cycle_rtol = cycle_rtol;
   c->lagnorm_tau = tau;
   c->gabs = 0.0;
 }
 
-hipError_t launch_residual(const Op& op, const double* b, const double* x, double* r,
-                           const Work& w, long long its_before, long long maxit, int m, int gs,
-                           int final_v, double tol, double tau, hipStream_t s) {
+hipError_t launch_residual(const Op& op, const double* b, const double* x, const Work& w,
+                           long long its_before, long long maxit, int m, int gs, int final_v,
+                           double tol, double tau, double cycle_rtol, hipStream_t s) {
   hipLaunchKernelGGL(cycle_begin_kernel, dim3(1), dim3(64), 0, s, w.ctl, its_before, maxit, m, gs,
-                     final_v, tol, tau);
+                     final_v, tol, tau, cycle_rtol);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return op_apply(op, x, r, b, nullptr, 0, s);
+  if (w.fp32) return op_apply<double, float>(op, x, w.V32, b, nullptr, 0, s);
+  return op_apply<double, double>(op, x, w.V, b, nullptr, 0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -715,6 +792,8 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
         w.coef_r1[0] = beta * out.ig * out.ig;
         ctl->gamma_prev = gamma;
         ctl->mode = run_mode;
+        // the Arnoldi-residual target of the cycle (read by this block only)
+        if (ctl->cycle_rtol > 0.0) ctl->tol_cyc = fmax(ctl->tol_abs, ctl->cycle_rtol * gamma);
       }
       ctl->mode_iter = 0;
     }
@@ -832,7 +911,7 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
     if (tid == 0) {
       int code = kRunning;
       if (brk) code = kBreakdown;
-      else if (ctl->gabs <= ctl->tol_abs) code = kConverged;
+      else if (ctl->gabs <= ctl->tol_cyc) code = kConverged;
       else if (j >= m) code = kFull;
       else if (ctl->its_before + j >= ctl->maxit) code = kMaxit;
       s_flag = code;
@@ -932,14 +1011,15 @@ static ReduceShape reduce_columns(int ncol) {
   return s;
 }
 
-// Rows per block (a multiple of 128, so that row pairs and 64-lane steps tile
-// a block's range) for at most max_blocks blocks.
+// Rows per block (a multiple of 256, so that 16-byte row vectors of doubles
+// or floats and 64-lane steps tile a block's range) for at most max_blocks
+// blocks.
 static void reduce_rows(ReduceShape& s, long long n, int max_blocks) {
-  long long nb = (n + 127) / 128;
+  long long nb = (n + 255) / 256;
   if (nb > max_blocks) nb = max_blocks;
   if (nb < 1) nb = 1;
   long long rpb = (n + nb - 1) / nb;
-  rpb = (rpb + 127) / 128 * 128;
+  rpb = (rpb + 255) / 256 * 256;
   s.rows_per_block = rpb;
   s.nblocks = (int)((n + rpb - 1) / rpb);
 }
@@ -947,71 +1027,74 @@ static void reduce_rows(ReduceShape& s, long long n, int max_blocks) {
 
 // One wave's share of the fused reduction for NC consecutive columns of V
 // (starting at vb): over the rows of its slice of [r0, r1),
-// ap[c] += V[r, c] u[r] and (Z) aq[c] += V[r, c] z[r].  NC and Z are
+// ap[c] += V[r, c] u[r] and (Z) aq[c] += V[r, c] z[r], products and sums in
+// FP64 whatever the element type T of V, u and z.  NC and Z are
 // compile-time, so every load of a row step is unconditional and the whole
 // step is in flight before the first FMA.
-template <int NC, bool VEC, bool Z>
-__device__ __forceinline__ void stream_cols(const double* __restrict__ vb, long long ldv,
-                                            const double* __restrict__ u,
-                                            const double* __restrict__ z, long long r0,
-                                            long long r1, int rw, int wr, int lane, double* ap,
-                                            double* aq) {
+template <int NC, bool VEC, bool Z, typename T>
+__device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long ldv,
+                                            const T* __restrict__ u, const T* __restrict__ z,
+                                            long long r0, long long r1, int rw, int wr, int lane,
+                                            double* ap, double* aq) {
   if constexpr (VEC) {
-    // Lane owns rows (r, r+1): 16-byte loads, V non-temporal.  Two-stage
-    // software pipeline: the loads of the next row step are issued before
-    // the FMAs of the current one, so a wave always has a step in flight.
-    const long long step = 2LL * wr * kWave;
-    long long r = r0 + 2LL * ((long long)rw * kWave + lane);
-    // Two register stages A and B alternate roles (no copies between them,
-    // which would force a wait on the loads in flight).  Without a next step
-    // the current rows are loaded again and not used, so the loads stay
-    // unconditional and each wait covers only the step being consumed.
-    dvec2 ua = {0.0, 0.0}, za = {0.0, 0.0}, va[NC];
-    dvec2 ub = {0.0, 0.0}, zb = {0.0, 0.0}, vn[NC];
+    // Lane owns W consecutive rows (one 16-byte load per column; V
+    // non-temporal).  Two-stage software pipeline: the loads of the next row
+    // step are issued before the FMAs of the current one, so a wave always
+    // has a step in flight.  The two register stages A and B alternate roles
+    // (no copies between them, which would force a wait on the loads in
+    // flight).  Without a next step the current rows are loaded again and
+    // not used, so the loads stay unconditional and each wait covers only
+    // the step being consumed.
+    typedef typename Vec16<T>::type VT;
+    constexpr int W = Vec16<T>::W;
+    const long long step = (long long)W * wr * kWave;
+    long long r = r0 + (long long)W * ((long long)rw * kWave + lane);
+    VT ua, za, va[NC], ub, zb, vn[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) va[c] = vn[c] = dvec2{0.0, 0.0};
-    auto load = [&](dvec2& uu, dvec2& zz, dvec2* vv, long long rr) {
-      uu = ld2(u + rr);
-      if constexpr (Z) zz = ld2(z + rr);
+    for (int e = 0; e < W; ++e) ua[e] = za[e] = ub[e] = zb[e] = T(0);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) vv[c] = ld_stream2(vb + (size_t)c * ldv + rr);
+    for (int c = 0; c < NC; ++c) va[c] = vn[c] = ua;
+    auto load = [&](VT& uu, VT& zz, VT* vv, long long rr) {
+      uu = ld16<T>(u + rr);
+      if constexpr (Z) zz = ld16<T>(z + rr);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) vv[c] = ld16_stream<T>(vb + (size_t)c * ldv + rr);
     };
-    auto consume = [&](const dvec2& uu, const dvec2& zz, const dvec2* vv) {
+    auto consume = [&](const VT& uu, const VT& zz, const VT* vv) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        ap[c] = fma(vv[c].x, uu.x, ap[c]);
-        ap[c] = fma(vv[c].y, uu.y, ap[c]);
-        if constexpr (Z) {
-          aq[c] = fma(vv[c].x, zz.x, aq[c]);
-          aq[c] = fma(vv[c].y, zz.y, aq[c]);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          ap[c] = fma((double)vv[c][e], (double)uu[e], ap[c]);
+          if constexpr (Z) aq[c] = fma((double)vv[c][e], (double)zz[e], aq[c]);
         }
       }
     };
-    if (r + 1 < r1) load(ua, za, va, r);
-    while (r + 1 < r1) {
+    if (r + W - 1 < r1) load(ua, za, va, r);
+    while (r + W - 1 < r1) {
       long long rn = r + step;
-      load(ub, zb, vn, (rn + 1 < r1) ? rn : r);
+      load(ub, zb, vn, (rn + W - 1 < r1) ? rn : r);
       consume(ua, za, va);
       r = rn;
-      if (!(r + 1 < r1)) break;
+      if (!(r + W - 1 < r1)) break;
       rn = r + step;
-      load(ua, za, va, (rn + 1 < r1) ? rn : r);
+      load(ua, za, va, (rn + W - 1 < r1) ? rn : r);
       consume(ub, zb, vn);
       r = rn;
     }
-    // an odd last row of the block's range
-    if (r < r1) {
-      const double uv = u[r];
-      const double zv = Z ? z[r] : 0.0;
+    // the last rows of the block's range that do not fill a vector
+    for (long long rr = r; rr < r1 && rr < r + W; ++rr) {
+      const double uv = (double)u[rr];
+      const double zv = Z ? (double)z[rr] : 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const double v = vb[(size_t)c * ldv + r];
+        const double v = (double)vb[(size_t)c * ldv + rr];
         ap[c] = fma(v, uv, ap[c]);
         if constexpr (Z) aq[c] = fma(v, zv, aq[c]);
       }
     }
   } else {
-    // any alignment: 8-byte loads, U row steps
+    // any alignment: element loads, U row steps
     constexpr int U = (NC >= 8) ? 1 : ((NC >= 4) ? 2 : 4);
     const long long step = (long long)wr * kWave;
     long long r = r0 + (long long)rw * kWave + lane;
@@ -1019,13 +1102,13 @@ __device__ __forceinline__ void stream_cols(const double* __restrict__ vb, long 
       double uu[U], zz[U], vv[U][NC];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        uu[q] = u[r + q * step];
-        if constexpr (Z) zz[q] = z[r + q * step];
+        uu[q] = (double)u[r + q * step];
+        if constexpr (Z) zz[q] = (double)z[r + q * step];
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) vv[q][c] = vb[(size_t)c * ldv + r + q * step];
+        for (int c = 0; c < NC; ++c) vv[q][c] = (double)vb[(size_t)c * ldv + r + q * step];
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
@@ -1037,11 +1120,11 @@ __device__ __forceinline__ void stream_cols(const double* __restrict__ vb, long 
       }
     }
     for (; r < r1; r += step) {
-      const double uv = u[r];
-      const double zv = Z ? z[r] : 0.0;
+      const double uv = (double)u[r];
+      const double zv = Z ? (double)z[r] : 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const double v = vb[(size_t)c * ldv + r];
+        const double v = (double)vb[(size_t)c * ldv + r];
         ap[c] = fma(v, uv, ap[c]);
         if constexpr (Z) aq[c] = fma(v, zv, aq[c]);
       }
@@ -1051,47 +1134,55 @@ __device__ __forceinline__ void stream_cols(const double* __restrict__ vb, long 
 
 // The partial column group (nc < CPW columns, the last one) dispatches to the
 // instantiation for its exact width.
-template <int CPW, bool VEC, bool Z>
-__device__ __forceinline__ void stream_group(int nc, const double* __restrict__ vb, long long ldv,
-                                             const double* __restrict__ u,
-                                             const double* __restrict__ z, long long r0,
+template <int CPW, bool VEC, bool Z, typename T>
+__device__ __forceinline__ void stream_group(int nc, const T* __restrict__ vb, long long ldv,
+                                             const T* __restrict__ u,
+                                             const T* __restrict__ z, long long r0,
                                              long long r1, int rw, int wr, int lane, double* ap,
                                              double* aq) {
   if (nc == CPW) {
-    stream_cols<CPW, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq);
+    stream_cols<CPW, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq);
     return;
   }
   if constexpr (CPW > 1) {
     switch (nc) {
-      case 1: stream_cols<1, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 2: if constexpr (CPW > 2) stream_cols<2, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 3: if constexpr (CPW > 3) stream_cols<3, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 4: if constexpr (CPW > 4) stream_cols<4, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 5: if constexpr (CPW > 5) stream_cols<5, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 6: if constexpr (CPW > 6) stream_cols<6, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 7: if constexpr (CPW > 7) stream_cols<7, VEC, Z>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 1: stream_cols<1, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 2: if constexpr (CPW > 2) stream_cols<2, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 3: if constexpr (CPW > 3) stream_cols<3, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 4: if constexpr (CPW > 4) stream_cols<4, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 5: if constexpr (CPW > 5) stream_cols<5, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 6: if constexpr (CPW > 6) stream_cols<6, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 7: if constexpr (CPW > 7) stream_cols<7, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
       default: break;
     }
   }
 }
 
-template <int CPW, bool VEC, bool Z>
+// The basis and A u in the element type of the step kernels.
+template <typename T> __host__ __device__ T* basis(const Work& w);
+template <> __host__ __device__ double* basis<double>(const Work& w) { return w.V; }
+template <> __host__ __device__ float* basis<float>(const Work& w) { return w.V32; }
+template <typename T> __host__ __device__ T* zvec(const Work& w);
+template <> __host__ __device__ double* zvec<double>(const Work& w) { return w.z; }
+template <> __host__ __device__ float* zvec<float>(const Work& w) { return w.z32; }
+
+template <int CPW, bool VEC, bool Z, typename T>
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
     Work w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr,
-    const double* __restrict__ Vraw, long long ldv_raw, const double* __restrict__ zraw,
+    const T* __restrict__ Vraw, long long ldv_raw, const T* __restrict__ zraw,
     double* __restrict__ raw_out) {
   extern __shared__ double lds[];
   const bool raw = (raw_out != nullptr);
   if (!raw && !ctl_runs(w.ctl, j)) return;
-  const double* __restrict__ V = raw ? Vraw : w.V;
+  const T* __restrict__ V = raw ? Vraw : basis<T>(w);
   const long long ldv = raw ? ldv_raw : w.ldv;
-  const double* __restrict__ z = raw ? zraw : w.z;
+  const T* __restrict__ z = raw ? zraw : zvec<T>(w);
   const int ncol = j + 1;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const long long r0 = (long long)blockIdx.x * rows_per_block;
   const long long r1 = min(n, r0 + rows_per_block);
-  const double* __restrict__ u = V + (size_t)j * ldv;
+  const T* __restrict__ u = V + (size_t)j * ldv;
   const int nchunk = (ncol + cpw - 1) / cpw;
   const int cw = wave % wc;
   const int rw = wave / wc;
@@ -1102,7 +1193,8 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
       double ap[CPW], aq[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
-      stream_group<CPW, VEC, Z>(nc, V + (size_t)c0 * ldv, ldv, u, z, r0, r1, rw, wr, lane, ap, aq);
+      stream_group<CPW, VEC, Z, T>(nc, V + (size_t)c0 * ldv, ldv, u, z, r0, r1, rw, wr, lane, ap,
+                                   aq);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         if (c < nc) {
@@ -1172,13 +1264,15 @@ static int resident_blocks(const void* kernel, int threads, size_t lds) {
   return r;
 }
 
-typedef void (*ReduceKernel)(Work, long long, int, long long, int, int, int, const double*,
-                             long long, const double*, double*);
+template <typename T>
+using ReduceKernel = void (*)(Work, long long, int, long long, int, int, int, const T*, long long,
+                              const T*, double*);
 
-static ReduceKernel pick_reduce(int tcpw, bool vec, bool z) {
+template <typename T>
+static ReduceKernel<T> pick_reduce(int tcpw, bool vec, bool z) {
   switch (tcpw * 4 + (vec ? 2 : 0) + (z ? 1 : 0)) {
 #define IGS_RED_CASE(C, VV, ZZ) \
-  case C * 4 + VV * 2 + ZZ: return reduce_kernel<C, VV, ZZ>;
+  case C * 4 + VV * 2 + ZZ: return reduce_kernel<C, VV, ZZ, T>;
 #define IGS_RED_CASES(C) \
   IGS_RED_CASE(C, 0, 0) IGS_RED_CASE(C, 0, 1) IGS_RED_CASE(C, 1, 0) IGS_RED_CASE(C, 1, 1)
     IGS_RED_CASES(1) IGS_RED_CASES(2) IGS_RED_CASES(4) IGS_RED_CASES(8)
@@ -1188,24 +1282,26 @@ static ReduceKernel pick_reduce(int tcpw, bool vec, bool z) {
   }
 }
 
-static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z,
-                                  const double* Vraw, long long ldv_raw, const double* zraw,
-                                  double* raw_out, hipStream_t s, int* nblocks_out) {
+template <typename T>
+static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z, const T* Vraw,
+                                  long long ldv_raw, const T* zraw, double* raw_out,
+                                  hipStream_t s, int* nblocks_out) {
   const int ncol = j + 1;
   ReduceShape sh = reduce_columns(ncol);
   const size_t lds = reduce_lds_bytes(sh, ncol);
-  // 16-byte row pairs need an even leading dimension and aligned columns
-  const double* Vp = raw_out ? Vraw : w.V;
-  const double* zp = raw_out ? zraw : w.z;
+  // 16-byte row vectors need a leading dimension of whole vectors and
+  // 16-byte aligned columns
+  const T* Vp = raw_out ? Vraw : basis<T>(w);
+  const T* zp = raw_out ? zraw : zvec<T>(w);
   const long long ldv = raw_out ? ldv_raw : w.ldv;
-  const bool vec = (ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
+  const bool vec = (ldv % Vec16<T>::W == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
                    (reinterpret_cast<uintptr_t>(zp) % 16 == 0);
-  ReduceKernel k = pick_reduce(sh.tcpw, vec, with_z);
+  ReduceKernel<T> k = pick_reduce<T>(sh.tcpw, vec, with_z);
   if (k == nullptr) return hipErrorInvalidValue;
   // One round of resident blocks.  The grid (and so the summation order) is
   // the one of the variant with z, so that the tail iteration, which has no
   // z, forms V^T u exactly as the others do.
-  int cap = resident_blocks(reinterpret_cast<const void*>(pick_reduce(sh.tcpw, vec, true)),
+  int cap = resident_blocks(reinterpret_cast<const void*>(pick_reduce<T>(sh.tcpw, vec, true)),
                             kReduceThreads, lds);
   if (cap > kMaxBlocks) cap = kMaxBlocks;
   // with one or two columns a block streams little: one block per CU keeps
@@ -1219,8 +1315,8 @@ static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z
   Work wa = w;
   long long na = n, rpb = sh.rows_per_block, ldva = ldv_raw;
   int ja = j, cpw = sh.cpw, wc = sh.wc, wr = sh.wr;
-  const double* va = Vraw;
-  const double* za = zraw;
+  const T* va = Vraw;
+  const T* za = zraw;
   double* oa = raw_out;
   void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &va, &ldva, &za, &oa};
   return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(sh.nblocks), dim3(kReduceThreads),
@@ -1229,7 +1325,9 @@ static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z
 
 hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,
                          int* nblocks_out) {
-  return reduce_dispatch(w, n, j, with_z, nullptr, 0, nullptr, nullptr, s, nblocks_out);
+  if (w.fp32)
+    return reduce_dispatch<float>(w, n, j, with_z, nullptr, 0, nullptr, nullptr, s, nblocks_out);
+  return reduce_dispatch<double>(w, n, j, with_z, nullptr, 0, nullptr, nullptr, s, nblocks_out);
 }
 
 hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j, const double* z,
@@ -1240,7 +1338,7 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
   w.gpart = gpart;
   w.pstride = pstride;
   w.tickets = tickets;
-  return reduce_dispatch(w, n, j, z != nullptr, V, ldv, z, out, s, nullptr);
+  return reduce_dispatch<double>(w, n, j, z != nullptr, V, ldv, z, out, s, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1253,11 +1351,21 @@ __host__ __device__ __forceinline__ size_t update_lds_doubles(int j) {
   return (size_t)2 * (j + 1) + (size_t)7 * (j + 2) + stage_count(j);
 }
 
-template <bool HAS_T, bool VEC>
+// Rows of one tile of the update: every thread owns two 16-byte row vectors
+// (4 rows of doubles or 8 of floats).
+template <typename T>
+__host__ __device__ constexpr long long update_tile_rows() {
+  return 2LL * Vec16<T>::W * kUpdateThreads;
+}
+
+template <bool HAS_T, bool VEC, typename T>
 __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
-    Work w, long long n, int j, int ngroups, double* __restrict__ Vraw, long long ldv_raw,
-    const double* __restrict__ zraw, const double* __restrict__ traw,
+    Work w, long long n, int j, int ngroups, T* __restrict__ Vraw, long long ldv_raw,
+    const T* __restrict__ zraw, const double* __restrict__ traw,
     const double* __restrict__ r1raw, double igraw, int raw) {
+  typedef typename Vec16<T>::type VT;
+  constexpr int W = Vec16<T>::W;
+  constexpr int R = 2 * W;   // rows per thread and tile
   extern __shared__ double sdyn[];
   double* sP = sdyn;                 // V_{0:j}^T u and u^T u
   double* sQ = sdyn + (j + 1);       // V_{0:j}^T z and u^T z
@@ -1266,9 +1374,9 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   const double* r1 = sm + 2 * (j + 2);
   int mode;
   double ig;
-  double* __restrict__ V;
+  T* __restrict__ V;
   long long ldv;
-  const double* __restrict__ z;
+  const T* __restrict__ z;
   if (raw) {
     mode = kUpdNormal;
     ig = igraw;
@@ -1282,9 +1390,9 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     __syncthreads();
   } else {
     if (!ctl_runs(w.ctl, j)) return;
-    V = w.V;
+    V = basis<T>(w);
     ldv = w.ldv;
-    z = w.z;
+    z = zvec<T>(w);
     // the reduction totals: the group rows it left, summed in a fixed order
     for (int v = threadIdx.x; v < 2 * (j + 1); v += blockDim.x) {
       double g8[8];
@@ -1307,128 +1415,141 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   const bool need_r = (mode == kUpdNormal);
   const bool fallback = (mode == kUpdFallback);
   const double rj = need_r ? r1[j] : 0.0;
-  double* __restrict__ vj = V + (size_t)j * ldv;
-  double* __restrict__ un = V + (size_t)(j + 1) * ldv;
-  constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
+  T* __restrict__ vj = V + (size_t)j * ldv;
+  T* __restrict__ un = V + (size_t)(j + 1) * ldv;
+  constexpr long long kTile = update_tile_rows<T>();
   const long long ntiles = (n + kTile - 1) / kTile;
   double s2 = 0.0;  // ||w||^2 partial (fallback only)
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     if constexpr (VEC) {
-      // Full tile: thread owns the row pairs p0 = 2t and p1 = 2t + 2*kUpdateThreads
-      // of the tile; V is streamed with 16-byte non-temporal loads.
+      // Full tile: the thread owns the row vectors at p0 = W t and
+      // p1 = p0 + W kUpdateThreads; V is streamed with 16-byte non-temporal
+      // loads, 4 columns at a time; products and sums in FP64.
       const long long tb = tile * kTile;
       if (tb + kTile <= n) {
-        const long long p0 = tb + 2LL * threadIdx.x;
-        const long long p1 = p0 + 2LL * kUpdateThreads;
-        dvec2 a0 = {0.0, 0.0}, a1 = {0.0, 0.0}, b0 = {0.0, 0.0}, b1 = {0.0, 0.0};
-        int c = 0;
-        for (; c + 4 <= j; c += 4) {
-          dvec2 v0[4], v1[4];
+        const long long p0 = tb + (long long)W * threadIdx.x;
+        const long long p1 = p0 + (long long)W * kUpdateThreads;
+        double a0[W], a1[W], b0[W], b1[W];
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) {
-            const double* vc = V + (size_t)(c + cc) * ldv;
-            v0[cc] = ld_stream2(vc + p0);
-            v1[cc] = ld_stream2(vc + p1);
-          }
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) {
-            const double tc = HAS_T ? t[c + cc] : 0.0;
-            const double rc = r1[c + cc];
-            if (HAS_T) {
-              a0.x = fma(v0[cc].x, tc, a0.x); a0.y = fma(v0[cc].y, tc, a0.y);
-              a1.x = fma(v1[cc].x, tc, a1.x); a1.y = fma(v1[cc].y, tc, a1.y);
-            }
-            b0.x = fma(v0[cc].x, rc, b0.x); b0.y = fma(v0[cc].y, rc, b0.y);
-            b1.x = fma(v1[cc].x, rc, b1.x); b1.y = fma(v1[cc].y, rc, b1.y);
-          }
-        }
-        for (; c < j; ++c) {
-          const double* vc = V + (size_t)c * ldv;
-          const dvec2 v0 = ld_stream2(vc + p0);
-          const dvec2 v1 = ld_stream2(vc + p1);
+        for (int e = 0; e < W; ++e) a0[e] = a1[e] = b0[e] = b1[e] = 0.0;
+        auto use = [&](const VT& v0, const VT& v1, int c) {
           const double tc = HAS_T ? t[c] : 0.0;
           const double rc = r1[c];
-          if (HAS_T) {
-            a0.x = fma(v0.x, tc, a0.x); a0.y = fma(v0.y, tc, a0.y);
-            a1.x = fma(v1.x, tc, a1.x); a1.y = fma(v1.y, tc, a1.y);
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            if (HAS_T) {
+              a0[e] = fma((double)v0[e], tc, a0[e]);
+              a1[e] = fma((double)v1[e], tc, a1[e]);
+            }
+            b0[e] = fma((double)v0[e], rc, b0[e]);
+            b1[e] = fma((double)v1[e], rc, b1[e]);
           }
-          b0.x = fma(v0.x, rc, b0.x); b0.y = fma(v0.y, rc, b0.y);
-          b1.x = fma(v1.x, rc, b1.x); b1.y = fma(v1.y, rc, b1.y);
+        };
+        int c = 0;
+        for (; c + 4 <= j; c += 4) {
+          VT v0[4], v1[4];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const T* vc = V + (size_t)(c + cc) * ldv;
+            v0[cc] = ld16_stream<T>(vc + p0);
+            v1[cc] = ld16_stream<T>(vc + p1);
+          }
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) use(v0[cc], v1[cc], c + cc);
         }
-        const dvec2 u0 = ld2(vj + p0);
-        const dvec2 u1 = ld2(vj + p1);
+        for (; c < j; ++c) {
+          const T* vc = V + (size_t)c * ldv;
+          use(ld16_stream<T>(vc + p0), ld16_stream<T>(vc + p1), c);
+        }
+        const VT u0 = ld16<T>(vj + p0);
+        const VT u1 = ld16<T>(vj + p1);
+        VT o0, o1;
         if (fallback) {
-          const dvec2 w0 = u0 - a0;
-          const dvec2 w1 = u1 - a1;
-          *reinterpret_cast<dvec2*>(vj + p0) = w0;
-          *reinterpret_cast<dvec2*>(vj + p1) = w1;
-          s2 = fma(w0.x, w0.x, s2); s2 = fma(w0.y, w0.y, s2);
-          s2 = fma(w1.x, w1.x, s2); s2 = fma(w1.y, w1.y, s2);
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            const double w0 = (double)u0[e] - a0[e];
+            const double w1 = (double)u1[e] - a1[e];
+            o0[e] = (T)w0;
+            o1[e] = (T)w1;
+            s2 = fma(w0, w0, s2);
+            s2 = fma(w1, w1, s2);
+          }
+          st16<T>(vj + p0, o0);
+          st16<T>(vj + p1, o1);
         } else {
-          const dvec2 n0 = (u0 - a0) * ig;
-          const dvec2 n1 = (u1 - a1) * ig;
-          *reinterpret_cast<dvec2*>(vj + p0) = n0;
-          *reinterpret_cast<dvec2*>(vj + p1) = n1;
+          double n0[W], n1[W];
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            n0[e] = ((double)u0[e] - a0[e]) * ig;
+            n1[e] = ((double)u1[e] - a1[e]) * ig;
+            o0[e] = (T)n0[e];
+            o1[e] = (T)n1[e];
+          }
+          st16<T>(vj + p0, o0);
+          st16<T>(vj + p1, o1);
           if (need_r) {
-            const dvec2 z0 = ld2(z + p0);
-            const dvec2 z1 = ld2(z + p1);
-            dvec2 o0, o1;
-            o0.x = z0.x * ig - b0.x - n0.x * rj; o0.y = z0.y * ig - b0.y - n0.y * rj;
-            o1.x = z1.x * ig - b1.x - n1.x * rj; o1.y = z1.y * ig - b1.y - n1.y * rj;
-            *reinterpret_cast<dvec2*>(un + p0) = o0;
-            *reinterpret_cast<dvec2*>(un + p1) = o1;
+            const VT z0 = ld16<T>(z + p0);
+            const VT z1 = ld16<T>(z + p1);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+              o0[e] = (T)((double)z0[e] * ig - b0[e] - n0[e] * rj);
+              o1[e] = (T)((double)z1[e] * ig - b1[e] - n1[e] * rj);
+            }
+            st16<T>(un + p0, o0);
+            st16<T>(un + p1, o1);
           }
         }
         continue;
       }
     }
+    // element path (partial tiles, or any alignment): R rows per thread
     const long long base = tile * kTile + threadIdx.x;
-    double at[kUpdateRows], ar[kUpdateRows];
+    double at[R], ar[R];
 #pragma unroll
-    for (int k = 0; k < kUpdateRows; ++k) at[k] = ar[k] = 0.0;
-    const bool full = base + (long long)(kUpdateRows - 1) * kUpdateThreads < n;
+    for (int k = 0; k < R; ++k) at[k] = ar[k] = 0.0;
+    const bool full = base + (long long)(R - 1) * kUpdateThreads < n;
     if (full) {
-      // four columns x kUpdateRows rows of loads in flight before any FMA
+      // four columns x R rows of loads in flight before any FMA
       int c = 0;
       for (; c + 4 <= j; c += 4) {
-        double vv[4][kUpdateRows];
+        double vv[4][R];
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
-          const double* __restrict__ vc = V + (size_t)(c + cc) * ldv + base;
+          const T* __restrict__ vc = V + (size_t)(c + cc) * ldv + base;
 #pragma unroll
-          for (int k = 0; k < kUpdateRows; ++k) vv[cc][k] = vc[k * kUpdateThreads];
+          for (int k = 0; k < R; ++k) vv[cc][k] = (double)vc[k * kUpdateThreads];
         }
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
           const double tc = HAS_T ? t[c + cc] : 0.0;
           const double rc = r1[c + cc];
 #pragma unroll
-          for (int k = 0; k < kUpdateRows; ++k) {
+          for (int k = 0; k < R; ++k) {
             if (HAS_T) at[k] = fma(vv[cc][k], tc, at[k]);
             ar[k] = fma(vv[cc][k], rc, ar[k]);
           }
         }
       }
       for (; c < j; ++c) {
-        const double* __restrict__ vc = V + (size_t)c * ldv + base;
+        const T* __restrict__ vc = V + (size_t)c * ldv + base;
         const double tc = HAS_T ? t[c] : 0.0;
         const double rc = r1[c];
 #pragma unroll
-        for (int k = 0; k < kUpdateRows; ++k) {
-          const double v = vc[k * kUpdateThreads];
+        for (int k = 0; k < R; ++k) {
+          const double v = (double)vc[k * kUpdateThreads];
           if (HAS_T) at[k] = fma(v, tc, at[k]);
           ar[k] = fma(v, rc, ar[k]);
         }
       }
     } else {
       for (int c = 0; c < j; ++c) {
-        const double* __restrict__ vc = V + (size_t)c * ldv + base;
+        const T* __restrict__ vc = V + (size_t)c * ldv + base;
         const double tc = HAS_T ? t[c] : 0.0;
         const double rc = r1[c];
 #pragma unroll
-        for (int k = 0; k < kUpdateRows; ++k) {
+        for (int k = 0; k < R; ++k) {
           if (base + k * kUpdateThreads < n) {
-            const double v = vc[k * kUpdateThreads];
+            const double v = (double)vc[k * kUpdateThreads];
             if (HAS_T) at[k] = fma(v, tc, at[k]);
             ar[k] = fma(v, rc, ar[k]);
           }
@@ -1436,17 +1557,17 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
       }
     }
 #pragma unroll
-    for (int k = 0; k < kUpdateRows; ++k) {
+    for (int k = 0; k < R; ++k) {
       const long long r = base + k * kUpdateThreads;
       if (r < n) {
         if (fallback) {
-          const double wv = vj[r] - at[k];
-          vj[r] = wv;
+          const double wv = (double)vj[r] - at[k];
+          vj[r] = (T)wv;
           s2 = fma(wv, wv, s2);
         } else {
-          const double v = (vj[r] - at[k]) * ig;
-          vj[r] = v;
-          if (need_r) un[r] = z[r] * ig - ar[k] - v * rj;
+          const double v = ((double)vj[r] - at[k]) * ig;
+          vj[r] = (T)v;
+          if (need_r) un[r] = (T)((double)z[r] * ig - ar[k] - v * rj);
         }
       }
     }
@@ -1501,12 +1622,11 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   }
 }
 
-// Tiles of kUpdateThreads * kUpdateRows rows, one round of resident blocks
-// striding over them (so that every block runs the small solve once), capped
-// so that the per-block partials of the fallback path fit their buffer.
-static unsigned update_grid(const void* kernel, long long n, size_t lds) {
-  const long long per = (long long)kUpdateThreads * kUpdateRows;
-  const long long tiles = (n + per - 1) / per;
+// Tiles of update_tile_rows<T>() rows, one round of resident blocks striding
+// over them (so that every block runs the small solve once), capped so that
+// the per-block partials of the fallback path fit their buffer.
+static unsigned update_grid(const void* kernel, long long n, long long tile_rows, size_t lds) {
+  const long long tiles = (n + tile_rows - 1) / tile_rows;
   long long cap = resident_blocks(kernel, kUpdateThreads, lds);
   if (cap > kMaxBlocks) cap = kMaxBlocks;
   if (cap < 1) cap = 1;
@@ -1517,22 +1637,31 @@ static unsigned update_grid(const void* kernel, long long n, size_t lds) {
   return (unsigned)g;
 }
 
-typedef void (*UpdateKernel)(Work, long long, int, int, double*, long long, const double*,
-                             const double*, const double*, double, int);
+template <typename T>
+using UpdateKernel = void (*)(Work, long long, int, int, T*, long long, const T*, const double*,
+                              const double*, double, int);
 
-static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t, bool vec,
-                                  int ngroups, double* Vraw, long long ldv_raw,
-                                  const double* zraw, const double* traw, const double* r1raw,
-                                  double igraw, int raw, hipStream_t s) {
-  UpdateKernel k = has_t ? (vec ? update_kernel<true, true> : update_kernel<true, false>)
-                         : (vec ? update_kernel<false, true> : update_kernel<false, false>);
+template <typename T>
+static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t, int ngroups,
+                                  T* Vraw, long long ldv_raw, const T* zraw, const double* traw,
+                                  const double* r1raw, double igraw, int raw, hipStream_t s) {
+  // 16-byte row vectors need a leading dimension of whole vectors and
+  // 16-byte aligned columns
+  const T* Vp = raw ? Vraw : basis<T>(w);
+  const T* zp = raw ? zraw : zvec<T>(w);
+  const long long ldv = raw ? ldv_raw : w.ldv;
+  const bool vec = (ldv % Vec16<T>::W == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(zp) % 16 == 0);
+  UpdateKernel<T> k = has_t ? (vec ? update_kernel<true, true, T> : update_kernel<true, false, T>)
+                            : (vec ? update_kernel<false, true, T> : update_kernel<false, false, T>);
   const size_t lds = update_lds_doubles(j) * sizeof(double);
-  const unsigned grid = update_grid(reinterpret_cast<const void*>(k), n, lds);
+  const unsigned grid =
+      update_grid(reinterpret_cast<const void*>(k), n, update_tile_rows<T>(), lds);
   Work wa = w;
   long long na = n, ldva = ldv_raw;
   int ja = j, nga = ngroups, rawa = raw;
-  double* va = Vraw;
-  const double* za = zraw;
+  T* va = Vraw;
+  const T* za = zraw;
   const double* ta = traw;
   const double* ra = r1raw;
   double iga = igraw;
@@ -1543,20 +1672,18 @@ static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t,
 
 hipError_t launch_update(const Work& w, long long n, int j, int gs, int ngroups, hipStream_t s) {
   // With one Gauss-Seidel sweep there is no second-sweep vector t, and the
-  // kernel variant without it skips one FMA stream.  16-byte accesses need
-  // an even leading dimension and 16-byte aligned columns.
-  const bool vec = (w.ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(w.V) % 16 == 0) &&
-                   (reinterpret_cast<uintptr_t>(w.z) % 16 == 0);
-  return update_dispatch(w, n, j, gs == 2, vec, ngroups, nullptr, 0, nullptr, nullptr, nullptr,
-                         0.0, 0, s);
+  // kernel variant without it skips one FMA stream.
+  if (w.fp32)
+    return update_dispatch<float>(w, n, j, gs == 2, ngroups, nullptr, 0, nullptr, nullptr,
+                                  nullptr, 0.0, 0, s);
+  return update_dispatch<double>(w, n, j, gs == 2, ngroups, nullptr, 0, nullptr, nullptr, nullptr,
+                                 0.0, 0, s);
 }
 
 hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
                              const double* t, const double* r1, double inv_gamma, hipStream_t s) {
   Work w{};
-  const bool vec = (ldv % 2 == 0) && (reinterpret_cast<uintptr_t>(V) % 16 == 0) &&
-                   (reinterpret_cast<uintptr_t>(z) % 16 == 0);
-  return update_dispatch(w, n, j, true, vec, 0, V, ldv, z, t, r1, inv_gamma, 1, s);
+  return update_dispatch<double>(w, n, j, true, 0, V, ldv, z, t, r1, inv_gamma, 1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1611,11 +1738,14 @@ hipError_t launch_lsq(const Work& w, int m, hipStream_t s) {
   return hipGetLastError();
 }
 
+// x += V_{0:J} y (x and y FP64; V in the basis element type T).
+template <typename T>
 __global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long long n,
                                                                 double* __restrict__ x) {
   const int J = load_agent(&w.ctl->J);
   if (J <= 0) return;
   const double* __restrict__ y = w.y;
+  const T* __restrict__ V = basis<T>(w);
   constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
   const long long ntiles = (n + kTile - 1) / kTile;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -1630,9 +1760,9 @@ __global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long lo
         double vv[4][kUpdateRows];
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
-          const double* __restrict__ vc = w.V + (size_t)(c + cc) * w.ldv + base;
+          const T* __restrict__ vc = V + (size_t)(c + cc) * w.ldv + base;
 #pragma unroll
-          for (int k = 0; k < kUpdateRows; ++k) vv[cc][k] = vc[k * kUpdateThreads];
+          for (int k = 0; k < kUpdateRows; ++k) vv[cc][k] = (double)vc[k * kUpdateThreads];
         }
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
@@ -1643,11 +1773,11 @@ __global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long lo
       }
     }
     for (; c < J; ++c) {
-      const double* __restrict__ vc = w.V + (size_t)c * w.ldv + base;
+      const T* __restrict__ vc = V + (size_t)c * w.ldv + base;
       const double yc = y[c];
 #pragma unroll
       for (int k = 0; k < kUpdateRows; ++k) {
-        if (base + k * kUpdateThreads < n) acc[k] = fma(vc[k * kUpdateThreads], yc, acc[k]);
+        if (base + k * kUpdateThreads < n) acc[k] = fma((double)vc[k * kUpdateThreads], yc, acc[k]);
       }
     }
 #pragma unroll
@@ -1662,7 +1792,12 @@ hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s) 
   const long long per = (long long)kUpdateThreads * kUpdateRows;
   long long g = (n + per - 1) / per;
   if (g > kMaxBlocks) g = kMaxBlocks;
-  hipLaunchKernelGGL(xupdate_kernel, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w, n, x);
+  if (w.fp32)
+    hipLaunchKernelGGL(xupdate_kernel<float>, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w, n,
+                       x);
+  else
+    hipLaunchKernelGGL(xupdate_kernel<double>, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w,
+                       n, x);
   return hipGetLastError();
 }
 

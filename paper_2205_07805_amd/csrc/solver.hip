@@ -56,8 +56,11 @@ struct igs_ctx {
   int* d_col = nullptr;
   double* d_vals = nullptr;
   double* d_A = nullptr;
+  float* d_vals32 = nullptr;   // CSR values rounded to FP32 (first mixed-precision solve)
+  double es_bytes = 8.0;       // bytes of a basis element in the current solve
 
   // workspace for restart length m_alloc
+  int m32_alloc = 0;           // columns + 1 of the FP32 basis (mixed precision)
   int m_alloc = 0;
   Work w{};
   Ctl* h_ctl = nullptr;  // pinned host copy of the control block
@@ -112,7 +115,7 @@ int set_err(igs_ctx* c, int code, const char* fmt, ...) {
 void free_workspace(igs_ctx* c) {
   Work& w = c->w;
   void* ptrs[] = {w.V, w.z, w.H, w.R, w.T, w.L, w.cs, w.sn, w.g, w.y, w.coef_t, w.coef_r1,
-                  w.part, w.gpart, w.tickets, w.ctl, c->d_V_first};
+                  w.part, w.gpart, w.tickets, w.ctl, c->d_V_first, w.V32, w.z32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
@@ -121,6 +124,7 @@ void free_workspace(igs_ctx* c) {
   c->V_first_cols = 0;
   c->w = Work{};
   c->m_alloc = 0;
+  c->m32_alloc = 0;
 }
 
 void free_raw(igs_ctx* c) {
@@ -175,6 +179,31 @@ int ensure_workspace(igs_ctx* c, int m) {
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   memset(c->h_ctl, 0, sizeof(Ctl));
   c->m_alloc = m;
+  return IGS_OK;
+}
+
+// FP32 basis and A u (same leading dimension as the FP64 basis) and the FP32
+// copy of the CSR values, for the mixed-precision cycles.
+int ensure_fp32(igs_ctx* c, int m) {
+  Work& w = c->w;
+  if (!c->d_vals32 && c->nnz > 0) {
+    float* v = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&v), sizeof(float) * c->nnz) != hipSuccess)
+      return set_err(c, IGS_ENOMEM, "cannot allocate %lld FP32 operator values", c->nnz);
+    c->d_vals32 = v;
+    HIP_OR_FAIL(c, igs::launch_round_to_float(c->d_vals, c->d_vals32, c->nnz, c->stream));
+    c->op.vals32 = c->d_vals32;
+  }
+  if (c->m32_alloc >= m + 1 && w.V32) return IGS_OK;
+  if (w.V32) (void)hipFree(w.V32);
+  if (w.z32) (void)hipFree(w.z32);
+  w.V32 = nullptr;
+  w.z32 = nullptr;
+  c->m32_alloc = 0;
+  if (hipMalloc(reinterpret_cast<void**>(&w.V32), sizeof(float) * w.ldv * (m + 1)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&w.z32), sizeof(float) * w.ldv) != hipSuccess)
+    return set_err(c, IGS_ENOMEM, "cannot allocate the FP32 basis (%lld x %d)", w.ldv, m + 1);
+  c->m32_alloc = m + 1;
   return IGS_OK;
 }
 
@@ -252,7 +281,7 @@ void mark_cycle(igs_ctx* c, int j_end, int m, int J, double dn) {
     bool ran = launch_ran(p.kernel, p.j, j_end, m);
     if (p.kernel == IGS_K_XUPDATE) {
       ran = J > 0;
-      p.bytes = 8.0 * dn * J + 16.0 * dn;
+      p.bytes = c->es_bytes * dn * J + 16.0 * dn;
     }
     p.ran = ran ? 1 : 0;
   }
@@ -439,7 +468,7 @@ extern "C" int igs_destroy(igs_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   free_workspace(c);
   free_raw(c);
-  void* ptrs[] = {c->d_row_ptr, c->d_col, c->d_vals, c->d_A};
+  void* ptrs[] = {c->d_row_ptr, c->d_col, c->d_vals, c->d_A, c->d_vals32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -481,7 +510,17 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   const bool prof = o.profile != 0;
   const int pmask = prof ? (o.profile_kernels ? o.profile_kernels : (1 << IGS_K_COUNT) - 1) : 0;
   const int final_v = o.final_basis_vector ? 1 : 0;
+  const bool fp32 = o.inner_fp32 != 0;
+  const double cycle_rtol = fp32 ? (o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5) : 0.0;
+  if (fp32) {
+    if (c->op.dense) return set_err(c, IGS_ENOTIMPL, "FP32 cycles need a CSR operator");
+    if (o.keep_first_basis)
+      return set_err(c, IGS_ENOTIMPL, "keep_first_basis is FP64 only (the basis is FP32)");
+    rc = ensure_fp32(c, m);
+    if (rc != IGS_OK) return rc;
+  }
   Work& w = c->w;
+  w.fp32 = fp32 ? 1 : 0;
   hipStream_t s = c->stream;
   c->J_first = -1;
   c->V_first_valid = 0;
@@ -494,10 +533,15 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     return set_err(c, IGS_EINVAL, "b or x0 holds %d non-finite entries", c->h_ctl->nonfinite_in);
   const double bnorm = c->h_ctl->bnorm;
 
-  // algorithmic bytes of each launch (minimum HBM traffic of its shape)
+  // algorithmic bytes of each launch (minimum HBM traffic of its shape);
+  // es: bytes of a basis element (8, or 4 in FP32 cycles)
   const double dn = (double)n;
-  const double op_bytes = c->op.dense ? 8.0 * dn * dn + 16.0 * dn
-                                      : 12.0 * (double)c->nnz + 4.0 * (dn + 1) + 16.0 * dn;
+  const double es = fp32 ? 4.0 : 8.0;
+  const double op64_bytes = c->op.dense ? 8.0 * dn * dn + 16.0 * dn
+                                        : 12.0 * (double)c->nnz + 4.0 * (dn + 1) + 16.0 * dn;
+  const double op_bytes = fp32 ? 8.0 * (double)c->nnz + 4.0 * (dn + 1) + 2.0 * es * dn
+                               : op64_bytes;
+  c->es_bytes = es;
 
   long long its = 0;
   int cycles = 0;
@@ -510,22 +554,24 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     const long long its_before = its;
     const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
     {
-      Timed tm(c, pmask, IGS_K_RESIDUAL, -1, cycles, op_bytes + 8.0 * dn);
-      HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w.V, w, its_before, maxit_cycle, m,
-                                          gs_iters, final_v, tol, tau, s));
+      Timed tm(c, pmask, IGS_K_RESIDUAL, -1, cycles, op64_bytes + es * dn);
+      HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w, its_before, maxit_cycle, m, gs_iters,
+                                          final_v, tol, tau, cycle_rtol, s));
     }
     // A check cycle (after the iteration budget) runs iteration 0 only: the
     // residual norm decides between convergence and giving up.
     const int jmax = final_check ? 0 : m;
     for (int j = 0; j <= jmax; ++j) {
-      const double* u = w.V + (size_t)j * w.ldv;
       if (j < m) {
         Timed tm(c, pmask, IGS_K_SPMV, j, cycles, op_bytes);
-        HIP_OR_FAIL(c, igs::launch_spmv(c->op, u, w.z, w.ctl, j, s));
+        if (fp32)
+          HIP_OR_FAIL(c, igs::launch_spmv32(c->op, w.V32 + (size_t)j * w.ldv, w.z32, w.ctl, j, s));
+        else
+          HIP_OR_FAIL(c, igs::launch_spmv(c->op, w.V + (size_t)j * w.ldv, w.z, w.ctl, j, s));
       }
       int nb = 0;
       {
-        Timed tm(c, pmask, IGS_K_REDUCE, j, cycles, 8.0 * dn * (j + 1) + (j < m ? 8.0 * dn : 0.0));
+        Timed tm(c, pmask, IGS_K_REDUCE, j, cycles, es * dn * (j + 1) + (j < m ? es * dn : 0.0));
         HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, s, &nb));
       }
       // The update kernel runs the small solve of iteration j in every block.
@@ -533,7 +579,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       // fallback there) and writes v_m on request; it never writes column
       // m + 1.
       {
-        Timed tm(c, pmask, IGS_K_UPDATE, j, cycles, 8.0 * dn * (j + 1) + 8.0 * dn + 16.0 * dn);
+        Timed tm(c, pmask, IGS_K_UPDATE, j, cycles, es * dn * (j + 1) + 3.0 * es * dn);
         HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_iters, igs::reduce_groups(nb), s));
       }
     }

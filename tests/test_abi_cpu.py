@@ -57,6 +57,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(igs_opts), offsetof(igs_opts, lagnorm_tau),
          offsetof(igs_opts, keep_first_basis), sizeof(igs_info), offsetof(igs_info, seconds));
   printf("%d %d\n", IGS_MAX_RESTART, IGS_K_COUNT);
+  printf("%zu %zu\n", offsetof(igs_opts, inner_fp32), offsetof(igs_opts, inner_rtol));
   return 0;
 }
 ''')
@@ -72,6 +73,7 @@ int main(void) {
     assert vals[4] == IgsInfo.seconds.offset
     from paper_2205_07805_amd import igs
     assert vals[5] == igs.IGS_MAX_RESTART and vals[6] == igs.IGS_K_COUNT
+    assert vals[7] == IgsOpts.inner_fp32.offset and vals[8] == IgsOpts.inner_rtol.offset
 
 
 def test_missing_library_fails_loudly(tmp_path):
