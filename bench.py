@@ -92,6 +92,45 @@ def cpu_baseline(a, b, restart, tol, n_iters):
                       f"cycles, one-reduce, two sweeps) of the same {a.n}-row solve, {dt:.1f} s"}
 
 
+def mixed_precision_compare(torch, W, Solver, igs, dev, steps, grid=96, restart=40, tol=5e-14):
+    """Solves per second of GMRES(restart) on the 3D convection-diffusion
+    system of side `grid` to tol (backward error about 7e-15), with FP64
+    cycles and with FP32 cycles inside FP64 restarts (iterative refinement).
+    The error of the FP32-cycle solution is stated against the FP64 one."""
+    a, b = W.make_convdiff3d(grid, 50.0)
+    s = Solver(a)
+    b_d = torch.as_tensor(b, device=dev)
+    x_d = torch.zeros_like(b_d)
+    out = {"workload": f"convdiff3d_N{grid}_Pe50_gmres{restart}_tol{tol:g}", "n": a.n,
+           "nnz": a.nnz}
+    xs = {}
+    try:
+        for name, fp32 in (("fp64", 0), ("fp32_cycles", 1)):
+            def one():
+                x_d.zero_()
+                with torch.cuda.stream(s.stream):
+                    return igs.igs_solve_opts(s.ctx, b_d, x_d, restart, tol, 2,
+                                              igs.IgsOpts(inner_fp32=fp32, maxit=20000))
+            rc, info = one()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rc, info = one()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            beta, _ = backward_error_torch(torch, a, b_d, x_d)
+            xs[name] = x_d.clone()
+            out[name] = {"rc": rc, "iters": info["iters"], "ms_per_solve": 1e3 * dt,
+                         "solves_per_s": 1.0 / dt, "iters_per_s": info["iters"] / dt,
+                         "backward_error": beta}
+        out["speedup"] = out["fp64"]["ms_per_solve"] / out["fp32_cycles"]["ms_per_solve"]
+        out["fp32_cycles_vs_fp64_max_rel_diff"] = float(
+            (xs["fp32_cycles"] - xs["fp64"]).abs().max() / xs["fp64"].abs().max())
+    finally:
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +142,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=180)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -196,6 +237,15 @@ def main():
     torch.cuda.synchronize()
     dt1 = time.perf_counter() - t1
 
+    # The same solver family on the 96^3 system with GMRES(40), to backward
+    # error 1e-14: FP64 cycles against FP32 cycles inside FP64 restarts.
+    mixed = None
+    if not args.no_mixed:
+        log("[bench] mixed precision on 96^3 ...")
+        mixed = mixed_precision_compare(torch, W, Solver, igs, dev, args.mixed_steps)
+        log(f"[bench] mixed: {mixed}")
+    s.close()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -229,10 +279,10 @@ def main():
         "roofline": roofline,
         "gs1": {"iters": info1["iters"], "seconds": dt1, "iters_per_s": info1["iters"] / dt1,
                 "converged": bool(info1["converged"])},
+        "mixed_precision": mixed,
         "cpu_baseline": cpu,
         "profiled": not args.no_profile,
     }
-    s.close()
     print(json.dumps(line), flush=True)
 
 
