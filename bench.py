@@ -177,11 +177,11 @@ def main():
     b_d = torch.as_tensor(b, device=dev)
     x_d = torch.zeros_like(b_d)
 
-    def solve(gs, profile_kernels=None):
+    def solve(gs, profile_kernels=None, **extra):
         x_d.zero_()
-        o = {}
+        o = dict(extra)
         if profile_kernels is not None and not args.no_profile:
-            o = {"profile": 1, "profile_kernels": profile_kernels}
+            o.update({"profile": 1, "profile_kernels": profile_kernels})
         with torch.cuda.stream(s.stream):
             return igs.igs_solve_opts(s.ctx, b_d, x_d, args.restart, args.tol, gs, igs.IgsOpts(**o))
 
@@ -237,6 +237,16 @@ def main():
     torch.cuda.synchronize()
     dt1 = time.perf_counter() - t1
 
+    # Comparator: the two-reduce Algorithm 4.1 with two sweeps (a second
+    # reduction and correction per iteration), same system and tolerance.
+    rc2, info2r = solve(2, two_reduce=1)
+    t2 = time.perf_counter()
+    rc2, info2r = solve(2, two_reduce=1)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t2
+    two_reduce = {"iters": info2r["iters"], "seconds": dt2, "iters_per_s": info2r["iters"] / dt2,
+                  "converged": bool(info2r["converged"])}
+
     # The same solver family on the 96^3 system with GMRES(40), to backward
     # error 1e-14: FP64 cycles against FP32 cycles inside FP64 restarts.
     mixed = None
@@ -279,6 +289,7 @@ def main():
         "roofline": roofline,
         "gs1": {"iters": info1["iters"], "seconds": dt1, "iters_per_s": info1["iters"] / dt1,
                 "converged": bool(info1["converged"])},
+        "two_reduce_gs2": two_reduce,
         "mixed_precision": mixed,
         "cpu_baseline": cpu,
         "profiled": not args.no_profile,

@@ -90,7 +90,13 @@ typedef struct igs_opts {
                            x = x0 + V y stay in FP64: iterative refinement with
                            one FP32 Arnoldi cycle per correction.  CSR
                            operators only (IGS_ENOTIMPL otherwise).            */
-  int reserved[2];
+  int two_reduce;       /* 1 with gs_iters = 2: the two-reduce Algorithm 4.1
+                           (Section 4): after the first sweep a second
+                           reduction r2 = V^T u, r3 = (I + L)^{-1} r2,
+                           w = u - V r3 and the column r1 + r3; two global
+                           reductions per iteration (a comparator for the
+                           one-reduce default)                                 */
+  int reserved[1];
   double inner_rtol;    /* inner_fp32: a cycle also ends once its Arnoldi
                            residual is <= inner_rtol * ||r0|| of the cycle;
                            <= 0 means 1e-5                                     */

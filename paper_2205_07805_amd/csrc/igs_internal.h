@@ -26,7 +26,8 @@ enum UpdateMode : int {
   kUpdNone = 0,      // nothing (cycle ended without needing v_j)
   kUpdNormal = 1,    // v_j and u_{j+1}
   kUpdVOnly = 2,     // v_j only (last vector of a cycle, on request)
-  kUpdFallback = 3   // lagged norm cancelled: w = u - V t, explicit ||w||, finish column
+  kUpdFallback = 3,  // lagged norm cancelled: w = u - V t, explicit ||w||, finish column
+  kUpdCorrect = 4    // two-reduce second sweep: w = u - V t in place, t = T r2
 };
 
 // Control block in device memory.  Written by block 0 of the update kernel
@@ -122,6 +123,11 @@ hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStre
                          int* nblocks_out);
 // ngroups: the group totals the reduction of iteration j left in w.gpart.
 hipError_t launch_update(const Work& w, long long n, int j, int gs, int ngroups, hipStream_t s);
+// Second Gauss-Seidel sweep of the two-reduce variant for the vector in
+// column j (after the reduction of [V_{0:j}, u]^T u): r2 = V_{0:j}^T u,
+// r3 = (I + L_{0:j})^{-1} r2, u -= V_{0:j} r3 in place, and r3 is added to
+// the stored first-sweep coefficients of column j-1.
+hipError_t launch_correct(const Work& w, long long n, int j, int ngroups, hipStream_t s);
 hipError_t launch_lsq(const Work& w, int m, hipStream_t s);
 hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s);
 

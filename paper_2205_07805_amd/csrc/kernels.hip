@@ -1358,11 +1358,31 @@ __host__ __device__ constexpr long long update_tile_rows() {
   return 2LL * Vec16<T>::W * kUpdateThreads;
 }
 
+// The coefficients of the two-reduce second sweep for the vector in column j
+// (every block; the publisher also adds them to the first-sweep
+// coefficients of column j-1): t = T_j P[0:j], from LDS when T is staged.
+__device__ void correct_coefs(const Work& w, int j, const double* P, double* sm, bool pub) {
+  double* st = sm;
+  double* stg = sm + 7 * (j + 2);
+  // staged when the update kernel's shared memory holds the staging area
+  if (stage_count(j) > 0) {
+    stage_copy(stg, w.T, tri_row(j));
+    __syncthreads();
+    tri_matvec<true>(stg, P, st, j);
+  } else {
+    tri_matvec<false>(w.T, P, st, j);
+  }
+  __syncthreads();
+  if (pub)
+    for (int i = threadIdx.x; i < j; i += blockDim.x) w.coef_r1[i] += st[i];
+}
+
 template <bool HAS_T, bool VEC, typename T>
 __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     Work w, long long n, int j, int ngroups, T* __restrict__ Vraw, long long ldv_raw,
     const T* __restrict__ zraw, const double* __restrict__ traw,
     const double* __restrict__ r1raw, double igraw, int raw) {
+  // raw: 1 = step kernel on caller buffers, 2 = two-reduce second sweep
   typedef typename Vec16<T>::type VT;
   constexpr int W = Vec16<T>::W;
   constexpr int R = 2 * W;   // rows per thread and tile
@@ -1377,7 +1397,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   T* __restrict__ V;
   long long ldv;
   const T* __restrict__ z;
-  if (raw) {
+  if (raw == 1) {
     mode = kUpdNormal;
     ig = igraw;
     V = Vraw;
@@ -1404,16 +1424,23 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
       sdyn[v] = acc;
     }
     __syncthreads();
-    const bool tail = (j >= w.ctl->m);
     const bool pub = (blockIdx.x == 0);
-    const StepCoefs c = (stage_count(j) > 0) ? small_solve<true>(w, n, j, tail, sP, sQ, sm, pub)
-                                             : small_solve<false>(w, n, j, tail, sP, sQ, sm, pub);
-    mode = c.mode;
-    ig = c.ig;
-    if (mode == kUpdNone) return;
+    if (raw == 2) {
+      correct_coefs(w, j, sP, sm, pub);
+      mode = kUpdCorrect;
+      ig = 1.0;
+    } else {
+      const bool tail = (j >= w.ctl->m);
+      const StepCoefs c = (stage_count(j) > 0) ? small_solve<true>(w, n, j, tail, sP, sQ, sm, pub)
+                                               : small_solve<false>(w, n, j, tail, sP, sQ, sm, pub);
+      mode = c.mode;
+      ig = c.ig;
+      if (mode == kUpdNone) return;
+    }
   }
   const bool need_r = (mode == kUpdNormal);
   const bool fallback = (mode == kUpdFallback);
+  const bool unscaled = fallback || (mode == kUpdCorrect);   // w = u - V t, stored as is
   const double rj = need_r ? r1[j] : 0.0;
   T* __restrict__ vj = V + (size_t)j * ldv;
   T* __restrict__ un = V + (size_t)(j + 1) * ldv;
@@ -1464,7 +1491,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
         const VT u0 = ld16<T>(vj + p0);
         const VT u1 = ld16<T>(vj + p1);
         VT o0, o1;
-        if (fallback) {
+        if (unscaled) {
 #pragma unroll
           for (int e = 0; e < W; ++e) {
             const double w0 = (double)u0[e] - a0[e];
@@ -1560,7 +1587,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     for (int k = 0; k < R; ++k) {
       const long long r = base + k * kUpdateThreads;
       if (r < n) {
-        if (fallback) {
+        if (unscaled) {
           const double wv = (double)vj[r] - at[k];
           vj[r] = (T)wv;
           s2 = fma(wv, wv, s2);
@@ -1647,9 +1674,9 @@ static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t,
                                   const double* r1raw, double igraw, int raw, hipStream_t s) {
   // 16-byte row vectors need a leading dimension of whole vectors and
   // 16-byte aligned columns
-  const T* Vp = raw ? Vraw : basis<T>(w);
-  const T* zp = raw ? zraw : zvec<T>(w);
-  const long long ldv = raw ? ldv_raw : w.ldv;
+  const T* Vp = (raw == 1) ? Vraw : basis<T>(w);
+  const T* zp = (raw == 1) ? zraw : zvec<T>(w);
+  const long long ldv = (raw == 1) ? ldv_raw : w.ldv;
   const bool vec = (ldv % Vec16<T>::W == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
                    (reinterpret_cast<uintptr_t>(zp) % 16 == 0);
   UpdateKernel<T> k = has_t ? (vec ? update_kernel<true, true, T> : update_kernel<true, false, T>)
@@ -1678,6 +1705,14 @@ hipError_t launch_update(const Work& w, long long n, int j, int gs, int ngroups,
                                   nullptr, 0.0, 0, s);
   return update_dispatch<double>(w, n, j, gs == 2, ngroups, nullptr, 0, nullptr, nullptr, nullptr,
                                  0.0, 0, s);
+}
+
+hipError_t launch_correct(const Work& w, long long n, int j, int ngroups, hipStream_t s) {
+  if (w.fp32)
+    return update_dispatch<float>(w, n, j, true, ngroups, nullptr, 0, nullptr, nullptr, nullptr,
+                                  1.0, 2, s);
+  return update_dispatch<double>(w, n, j, true, ngroups, nullptr, 0, nullptr, nullptr, nullptr,
+                                 1.0, 2, s);
 }
 
 hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,

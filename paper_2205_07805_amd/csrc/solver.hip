@@ -511,6 +511,10 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   const int pmask = prof ? (o.profile_kernels ? o.profile_kernels : (1 << IGS_K_COUNT) - 1) : 0;
   const int final_v = o.final_basis_vector ? 1 : 0;
   const bool fp32 = o.inner_fp32 != 0;
+  // two-reduce with two sweeps: the one-sweep step plus a second reduction
+  // and correction per iteration
+  const bool two_reduce = o.two_reduce != 0 && gs_iters == 2;
+  const int gs_step = two_reduce ? 1 : gs_iters;
   const double cycle_rtol = fp32 ? (o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5) : 0.0;
   if (fp32) {
     if (c->op.dense) return set_err(c, IGS_ENOTIMPL, "FP32 cycles need a CSR operator");
@@ -555,7 +559,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
     {
       Timed tm(c, pmask, IGS_K_RESIDUAL, -1, cycles, op64_bytes + es * dn);
-      HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w, its_before, maxit_cycle, m, gs_iters,
+      HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w, its_before, maxit_cycle, m, gs_step,
                                           final_v, tol, tau, cycle_rtol, s));
     }
     // A check cycle (after the iteration budget) runs iteration 0 only: the
@@ -580,7 +584,13 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       // m + 1.
       {
         Timed tm(c, pmask, IGS_K_UPDATE, j, cycles, es * dn * (j + 1) + 3.0 * es * dn);
-        HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_iters, igs::reduce_groups(nb), s));
+        HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_step, igs::reduce_groups(nb), s));
+      }
+      if (two_reduce && j < m && !final_check) {
+        // second sweep on u_{j+1}: r2 = [V_{0:j+1}, u]^T u, then the correction
+        int nb2 = 0;
+        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j + 1, false, s, &nb2));
+        HIP_OR_FAIL(c, igs::launch_correct(w, n, j + 1, igs::reduce_groups(nb2), s));
       }
     }
     if (!final_check) {

@@ -31,7 +31,8 @@ EXPORTED = (
 class IgsOpts(ctypes.Structure):
     _fields_ = [("maxit", c_int64), ("lagnorm_tau", c_double), ("final_basis_vector", c_int),
                 ("profile", c_int), ("max_cycles", c_int), ("keep_first_basis", c_int),
-                ("profile_kernels", c_int), ("inner_fp32", c_int), ("reserved", c_int * 2),
+                ("profile_kernels", c_int), ("inner_fp32", c_int), ("two_reduce", c_int),
+                ("reserved", c_int * 1),
                 ("inner_rtol", c_double)]
 
 

@@ -258,3 +258,46 @@ def test_dense_nonnormal_4096_full_gmres_200(torch):
     assert D.orthogonality_loss(V[:, : J + 1]) <= max(1e-13, 10 * loss_ref)
     assert D.arnoldi_relation_residual(op, V[:, : J + 1], H, anorm) < 1e-13
     assert_H_close(H, ref.H, ncols=10, tol=1e-11)
+
+
+@pytest.mark.parametrize("tol,beta_max", [(1e-12, 1e-12), (1e-13, 1e-14)])
+def test_two_reduce_gs2_convdiff2d_32_parity(torch, tol, beta_max):
+    """The two-reduce Algorithm 4.1 with two sweeps (second reduction and
+    correction per iteration) against the oracle's Algorithm 4.1."""
+    a, b = W.make_convdiff2d_32()
+    print(f"two-reduce gs=2 convdiff2d_32 tol={tol}", flush=True)
+    x, rc, info, H, _ = gpu(a, b, 50, tol, 2, two_reduce=1)
+    ref = O.gmres(a, b, restart=50, tol=tol, variant="igs2r", gs_iters=2)
+    op = O.as_operator(a)
+    assert rc == 0 and info["converged"] == 1
+    assert abs(info["iters"] - ref.iters) <= 2, (info["iters"], ref.iters)
+    assert np.linalg.norm(b - op.matvec(x)) / np.linalg.norm(b) <= tol
+    assert D.backward_error(op, b, x, D.norm2(op)) <= beta_max
+    assert_H_close(H, ref.first_cycle.H)
+    np.testing.assert_allclose(x, ref.x, rtol=0, atol=1e2 * tol * np.abs(ref.x).max())
+
+
+def test_two_reduce_gs2_dense_orthogonality(torch):
+    """Simoncini's matrix, one cycle of 99 iterations: two sweeps keep the
+    basis orthogonal to O(eps) (Section 4) with two reductions as with one."""
+    a, b, m, anorm = DENSE["simoncini"]
+    print("two-reduce gs=2 simoncini", flush=True)
+    x, rc, info, H, V = gpu(a, b, m, 0.0, 2, two_reduce=1, max_cycles=1, keep_first_basis=1,
+                            final_basis_vector=1)
+    ref = O.gmres(a, b, restart=m, tol=0.0, variant="igs2r", gs_iters=2, max_cycles=1).first_cycle
+    J = info["first_cycle_J"]
+    assert J == ref.J
+    op = O.as_operator(a)
+    assert D.orthogonality_loss(V[:, : J + 1]) < 1e-13
+    assert D.arnoldi_relation_residual(op, V[:, : J + 1], H, anorm) < 1e-13
+    assert_H_close(H, ref.H, ncols=10, tol=1e-11)
+
+
+def test_two_reduce_gs2_convdiff3d_ragged(torch):
+    a = W.convdiff3d(37, 50.0)
+    b = W.rhs_normal(a.n, 0)
+    print("two-reduce gs=2 convdiff3d_37", flush=True)
+    x, rc, info, H, _ = gpu(a, b, 30, 1e-10, 2, two_reduce=1)
+    ref = O.gmres(a, b, restart=30, tol=1e-10, variant="igs2r", gs_iters=2)
+    assert rc == 0 and abs(info["iters"] - ref.iters) <= 2
+    assert_H_close(H, ref.first_cycle.H)
