@@ -131,6 +131,57 @@ def mixed_precision_compare(torch, W, Solver, igs, dev, steps, grid=96, restart=
     return out
 
 
+def serving_compare(W, serve, count, slots, mem_cap=64 << 30, restart=50, tol=1e-12):
+    """The serving trace (2D convection-diffusion, sides uniform on [32, 512],
+    Pe uniform on [1, 100], Poisson arrivals at 200/s, b seeded per request)
+    served three ways through igs_serve: the plain FP64 solver one request at
+    a time (a queue alone), continuous batching over `slots` streams in FP64,
+    and the same with FP32 cycles inside FP64 restarts.  Latency is completion
+    minus arrival; throughput is requests over the time to the last
+    completion.  Every result's relative residual is checked on the host with
+    scipy (relres <= tol implies backward error <= tol)."""
+    import scipy.sparse as sp
+    trace = W.serving_trace(count=count, seed=7)
+
+    def solve_bytes(q, iters):
+        # algorithmic HBM bytes of `iters` Arnoldi iterations, cycles of
+        # `restart` columns: reduction 8n(j+2), update 8n(j+1) + 24n, operator
+        # apply 12 nnz + 4(n+1) + 16n at column j
+        n, nnz = q.a.n, q.a.nnz
+        full, rest = divmod(int(iters), restart)
+        def cols(k):   # sum over j < k of the per-iteration bytes
+            return 16.0 * n * (k * (k - 1) / 2) + k * (8.0 * n * 3 + 24.0 * n + 12.0 * nnz
+                                                        + 4.0 * (n + 1) + 16.0 * n)
+        return full * cols(restart) + cols(rest)
+
+    systems = [(q.a, q.b, q.arrival) for q in trace]
+    mats = [sp.csr_matrix((q.a.vals, q.a.col_idx, q.a.row_ptr), shape=(q.a.n, q.a.n)) for q in trace]
+    out = {"workload": f"{W.SERVING.name}_{count}req_gmres{restart}_tol{tol:g}",
+           "requests": count, "slots": slots, "mem_cap_bytes": mem_cap,
+           "n_range": [min(q.a.n for q in trace), max(q.a.n for q in trace)],
+           "arrival_window_s": trace[-1].arrival}
+    for name, k, fp32 in (("fp64_serial", 1, 0), ("fp64_batched", slots, 0),
+                          ("fp32_cycles_batched", slots, 1)):
+        res, wall, rc = serve(systems, slots=k, mem_cap=mem_cap, restart=restart, tol=tol,
+                              gs_iters=2, inner_fp32=fp32, maxit=200000)
+        lat = np.array([r["t_done"] - r["arrival"] for r in res])
+        rel = max(float(np.linalg.norm(q.b - A @ r["x"]) / np.linalg.norm(q.b))
+                  for q, A, r in zip(trace, mats, res))
+        out[name] = {"slots": k, "rc": rc, "failed": sum(1 for r in res if r["rc"] != 0),
+                     "wall_s": wall, "solves_per_s": count / wall,
+                     "iters_total": int(sum(r["iters"] for r in res)),
+                     "hbm_GBs_algorithmic": sum(solve_bytes(q, r["iters"])
+                                                for q, r in zip(trace, res)) / wall / 1e9,
+                     "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+                     "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+                     "max_relres": rel}
+        log(f"[bench] serving {name}: {out[name]}")
+    base = out["fp64_serial"]["solves_per_s"]
+    for name in ("fp64_batched", "fp32_cycles_batched"):
+        out[name]["throughput_vs_fp64_serial"] = out[name]["solves_per_s"] / base
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +195,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--mixed-steps", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -256,6 +310,12 @@ def main():
         log(f"[bench] mixed: {mixed}")
     s.close()
 
+    serving = None
+    if not args.no_serve:
+        from paper_2205_07805_amd import serve
+        log(f"[bench] serving {args.serve_requests} requests ...")
+        serving = serving_compare(W, serve, args.serve_requests, args.serve_slots)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -291,6 +351,7 @@ def main():
                 "converged": bool(info1["converged"])},
         "two_reduce_gs2": two_reduce,
         "mixed_precision": mixed,
+        "serving": serving,
         "cpu_baseline": cpu,
         "profiled": not args.no_profile,
     }

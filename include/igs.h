@@ -173,6 +173,55 @@ const char *igs_last_error(const igs_ctx *ctx);
 /* Largest supported restart length. */
 #define IGS_MAX_RESTART 512
 
+/* ---- Serving: continuous batching of independent solves ------------------ */
+
+/* One request of a serving trace: a CSR system A x = b (host arrays, the same
+ * format and checks as igs_create) that arrives `arrival` seconds after the
+ * start of igs_serve.  The caller owns every array; x receives the solution
+ * (from x0 = 0).  Outputs: t_admit and t_done (seconds after the start; -1
+ * when the request never ran), iters, rc (the igs_solve_opts return value)
+ * and status (IGS_CYCLE_* of its last cycle). */
+typedef struct igs_request {
+  int64_t n, nnz;
+  const int32_t *row_ptr, *col_idx;
+  const double *vals, *b;
+  double *x;
+  double arrival;
+  double t_admit, t_done;  /* out */
+  int64_t iters;           /* out */
+  int rc;                  /* out */
+  int status;              /* out */
+} igs_request;
+
+/*
+ * Serve a trace of independent GMRES(restart) solves on the current device
+ * with continuous batching: a request joins a FIFO queue at its arrival time
+ * and is admitted as soon as one of `slots` solver slots is free and the
+ * device memory it holds (its operator, b, x, the Krylov basis V and the
+ * Hessenberg and triangular matrices, kept resident while it runs) fits
+ * within mem_cap bytes together with the requests already running.  Each slot
+ * owns a stream and a context sized for the largest request, so admitted
+ * solves overlap on the device and the loop allocates nothing per request.
+ * A request's result does not depend on what runs beside it (every kernel
+ * reduces in a fixed order): x is bit-identical to a lone igs_solve_opts of
+ * the same system with the same arguments.
+ *   tol, gs_iters, opts: as igs_solve_opts (opts may be NULL; profile and
+ *     keep_first_basis are ignored).  *wall_seconds: time from the start to
+ *     the last completion (may be NULL).
+ * The memory a request holds is 12 nnz + 4 (n+1) + 8 n (m'+5) + 32 (m'+2)^2
+ * bytes with m' = min(restart, n), plus 4 nnz + 4 n (m'+2) with inner_fp32
+ * (the FP32 basis and values).  The slots themselves hold `slots` times
+ * the footprint of the largest request, allocated once at the start.
+ * Returns IGS_OK when the trace was served: each request's rc tells its own
+ * outcome (IGS_EINVAL for a malformed CSR, IGS_ENOCONV, ...), and the other
+ * requests run regardless.  IGS_EINVAL for bad arguments or a request larger
+ * than mem_cap, IGS_ENOMEM/IGS_EDEVICE when the slots cannot be set up
+ * (nothing ran in these cases; message in igs_last_error(NULL)), IGS_EDEVICE
+ * when a request hit a device error.
+ */
+int igs_serve(igs_request *reqs, int nreq, int slots, int64_t mem_cap, int restart,
+              double tol, int gs_iters, const igs_opts *opts, double *wall_seconds);
+
 /* ---- Inspection of the FIRST restart cycle of the last solve (tests) ----- */
 
 /* Copy the Hessenberg matrix H (before Givens rotation) of the first cycle to

@@ -10,9 +10,14 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 using igs::Ctl;
@@ -57,6 +62,7 @@ struct igs_ctx {
   double* d_vals = nullptr;
   double* d_A = nullptr;
   float* d_vals32 = nullptr;   // CSR values rounded to FP32 (first mixed-precision solve)
+  long long n_cap = 0, nnz_cap = 0;  // serving slot: device capacity for rebinding operators
   double es_bytes = 8.0;       // bytes of a basis element in the current solve
 
   // workspace for restart length m_alloc
@@ -187,9 +193,11 @@ int ensure_workspace(igs_ctx* c, int m) {
 int ensure_fp32(igs_ctx* c, int m) {
   Work& w = c->w;
   if (!c->d_vals32 && c->nnz > 0) {
+    // a serving slot sizes the copy for the largest operator it will hold
+    const long long nv = c->nnz_cap > c->nnz ? c->nnz_cap : c->nnz;
     float* v = nullptr;
-    if (hipMalloc(reinterpret_cast<void**>(&v), sizeof(float) * c->nnz) != hipSuccess)
-      return set_err(c, IGS_ENOMEM, "cannot allocate %lld FP32 operator values", c->nnz);
+    if (hipMalloc(reinterpret_cast<void**>(&v), sizeof(float) * nv) != hipSuccess)
+      return set_err(c, IGS_ENOMEM, "cannot allocate %lld FP32 operator values", nv);
     c->d_vals32 = v;
     HIP_OR_FAIL(c, igs::launch_round_to_float(c->d_vals, c->d_vals32, c->nnz, c->stream));
     c->op.vals32 = c->d_vals32;
@@ -767,5 +775,217 @@ extern "C" int igs_profile_reset(igs_ctx* c) {
   if (!c) return IGS_EINVAL;
   harvest(c, true);
   for (KStat& s : c->stats) s = KStat{};
+  return IGS_OK;
+}
+
+// ===========================================================================
+// Serving: continuous batching of independent solves
+// ===========================================================================
+
+namespace {
+
+// Device memory a request holds while it runs: its operator, b and x, and the
+// basis and Hessenberg workspace of GMRES(m).
+long long request_bytes(long long n, long long nnz, int m, bool fp32) {
+  const long long mm = std::min<long long>(m, n);
+  return 12 * nnz + 4 * (n + 1) + 8 * n * (mm + 5) + 32 * (mm + 2) * (mm + 2) +
+         (fp32 ? 4 * nnz + 4 * n * (mm + 2) : 0);
+}
+
+// A serving slot: a context with device capacity for CSR operators of up to
+// n_cap rows and nnz_cap entries at restart m, plus b and x, on its own
+// stream.  Requests are bound to it one at a time, so the serving loop
+// allocates and frees no device memory (a free would wait for every stream).
+struct Slot {
+  hipStream_t stream = nullptr;
+  igs_ctx* ctx = nullptr;
+  double* b = nullptr;
+  double* x = nullptr;
+};
+
+int slot_create(Slot& sl, long long n_cap, long long nnz_cap, int m) {
+  if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
+    return set_err(nullptr, IGS_EDEVICE, "cannot create a stream");
+  igs_ctx* c = nullptr;
+  igs_ctx* out = nullptr;
+  int rc = common_create(&out, sl.stream, &c);
+  if (rc != IGS_OK) return rc;
+  sl.ctx = c;
+  c->n = n_cap;
+  c->nnz = nnz_cap;
+  c->n_cap = n_cap;
+  c->nnz_cap = nnz_cap;
+  if (dalloc(&c->d_row_ptr, n_cap + 1) != hipSuccess ||
+      dalloc(&c->d_col, std::max<long long>(nnz_cap, 1)) != hipSuccess ||
+      dalloc(&c->d_vals, std::max<long long>(nnz_cap, 1)) != hipSuccess ||
+      dalloc(&sl.b, n_cap) != hipSuccess || dalloc(&sl.x, n_cap) != hipSuccess)
+    return set_err(nullptr, IGS_ENOMEM, "device allocation of a serving slot failed");
+  c->op.dense = 0;
+  c->op.row_ptr = c->d_row_ptr;
+  c->op.col_idx = c->d_col;
+  c->op.vals = c->d_vals;
+  rc = ensure_workspace(c, (int)std::min<long long>(m, std::min<long long>(n_cap, IGS_MAX_RESTART)));
+  if (rc != IGS_OK) return set_err(nullptr, rc, "%s", c->err.c_str());
+  return IGS_OK;
+}
+
+void slot_destroy(Slot& sl) {
+  if (sl.b) (void)hipFree(sl.b);
+  if (sl.x) (void)hipFree(sl.x);
+  if (sl.ctx) igs_destroy(sl.ctx);
+  if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  sl = Slot{};
+}
+
+// Bind a host CSR operator to a slot (validated, copied on the slot's stream).
+int slot_bind(igs_ctx* c, long long n, long long nnz, const int32_t* rp, const int32_t* ci,
+              const double* va) {
+  if (n < 1 || n > c->n_cap || nnz < 0 || nnz > c->nnz_cap || !rp || (nnz > 0 && (!ci || !va)))
+    return set_err(c, IGS_EINVAL, "request of n = %lld, nnz = %lld exceeds the slot", n, nnz);
+  const int rc = validate_csr(c, n, nnz, rp, ci, va);
+  if (rc != IGS_OK) return rc;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_row_ptr, rp, sizeof(int32_t) * (n + 1),
+                                hipMemcpyHostToDevice, c->stream));
+  if (nnz > 0) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->d_col, ci, sizeof(int32_t) * nnz, hipMemcpyHostToDevice,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->d_vals, va, sizeof(double) * nnz, hipMemcpyHostToDevice,
+                                  c->stream));
+  }
+  const double avg = (double)nnz / (double)n;
+  int lpr = 1;
+  while (lpr < 64 && (double)lpr < avg) lpr *= 2;
+  c->n = n;
+  c->nnz = nnz;
+  c->op.n = n;
+  c->op.lpr = lpr;
+  if (c->d_vals32) {   // FP32 values of the previous operator: round the new ones
+    HIP_OR_FAIL(c, igs::launch_round_to_float(c->d_vals, c->d_vals32, nnz, c->stream));
+  }
+  return IGS_OK;
+}
+
+}  // namespace
+
+extern "C" int igs_serve(igs_request* reqs, int nreq, int slots, int64_t mem_cap, int restart,
+                         double tol, int gs_iters, const igs_opts* opts, double* wall_seconds) {
+  if (!reqs || nreq < 0 || slots < 1 || mem_cap <= 0 || restart < 1)
+    return set_err(nullptr, IGS_EINVAL, "invalid serving arguments");
+  if (nreq == 0) return IGS_OK;
+  igs_opts o{};
+  if (opts) o = *opts;
+  o.keep_first_basis = 0;
+  o.profile = 0;
+  long long n_cap = 1, nnz_cap = 0;
+  std::vector<long long> need(nreq);
+  for (int i = 0; i < nreq; ++i) {
+    reqs[i].rc = IGS_EINVAL;
+    reqs[i].iters = 0;
+    reqs[i].status = 0;
+    reqs[i].t_admit = reqs[i].t_done = -1.0;
+    if (reqs[i].n < 1 || reqs[i].nnz < 0 || !reqs[i].b || !reqs[i].x)
+      return set_err(nullptr, IGS_EINVAL, "request %d: invalid size or NULL array", i);
+    n_cap = std::max<long long>(n_cap, reqs[i].n);
+    nnz_cap = std::max<long long>(nnz_cap, reqs[i].nnz);
+    need[i] = request_bytes(reqs[i].n, reqs[i].nnz, restart, o.inner_fp32 != 0);
+    if (need[i] > mem_cap)
+      return set_err(nullptr, IGS_EINVAL, "request %d needs %lld bytes, more than the cap", i,
+                     need[i]);
+  }
+  std::vector<Slot> sl(slots);
+  for (int k = 0; k < slots; ++k) {
+    const int rc = slot_create(sl[k], n_cap, nnz_cap, restart);
+    if (rc != IGS_OK) {
+      for (Slot& x : sl) slot_destroy(x);
+      return rc;
+    }
+  }
+  std::vector<int> order(nreq);
+  for (int i = 0; i < nreq; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return reqs[a].arrival < reqs[b].arrival; });
+
+  // Shared state: the FIFO of arrived requests and the device memory they hold.
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<int> queue;
+  long long reserved = 0;
+  bool closed = false;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto since = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  int device = 0;
+  (void)hipGetDevice(&device);
+
+  auto worker = [&](int k) {
+    (void)hipSetDevice(device);
+    Slot& me = sl[k];
+    while (true) {
+      int i = -1;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        // admit the oldest arrived request once its memory fits the budget
+        cv.wait(lk, [&] {
+          return (!queue.empty() && reserved + need[queue.front()] <= mem_cap) ||
+                 (closed && queue.empty());
+        });
+        if (queue.empty()) break;
+        i = queue.front();
+        queue.pop_front();
+        reserved += need[i];
+      }
+      igs_request& r = reqs[i];
+      r.t_admit = since();
+      int rc = slot_bind(me.ctx, r.n, r.nnz, r.row_ptr, r.col_idx, r.vals);
+      igs_info info{};
+      if (rc == IGS_OK &&
+          (hipMemcpyAsync(me.b, r.b, sizeof(double) * r.n, hipMemcpyHostToDevice, me.stream) !=
+               hipSuccess ||
+           hipMemsetAsync(me.x, 0, sizeof(double) * r.n, me.stream) != hipSuccess))
+        rc = IGS_EDEVICE;
+      if (rc == IGS_OK) rc = igs_solve_opts(me.ctx, me.b, me.x, restart, tol, gs_iters, &o, &info);
+      if (rc == IGS_OK || rc == IGS_ENOCONV) {
+        if (hipMemcpyAsync(r.x, me.x, sizeof(double) * r.n, hipMemcpyDeviceToHost, me.stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(me.stream) != hipSuccess)
+          rc = IGS_EDEVICE;
+      }
+      r.rc = rc;
+      r.iters = info.iters;
+      r.status = info.last_cycle_status;
+      r.t_done = since();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        reserved -= need[i];
+      }
+      cv.notify_all();
+    }
+  };
+  std::vector<std::thread> threads;
+  threads.reserve(slots);
+  for (int k = 0; k < slots; ++k) threads.emplace_back(worker, k);
+  // arrivals: each request joins the queue at its arrival time
+  for (int idx = 0; idx < nreq; ++idx) {
+    const int i = order[idx];
+    const double at = reqs[i].arrival;
+    std::this_thread::sleep_until(t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                           std::chrono::duration<double>(at > 0 ? at : 0.0)));
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      queue.push_back(i);
+    }
+    cv.notify_all();
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    closed = true;
+  }
+  cv.notify_all();
+  for (std::thread& t : threads) t.join();
+  if (wall_seconds) *wall_seconds = since();
+  for (Slot& x : sl) slot_destroy(x);
+  for (int i = 0; i < nreq; ++i)
+    if (reqs[i].rc == IGS_EDEVICE) return IGS_EDEVICE;
   return IGS_OK;
 }

@@ -25,6 +25,7 @@ EXPORTED = (
     "igs_create", "igs_create_dense", "igs_solve", "igs_solve_opts", "igs_destroy",
     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
     "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
+    "igs_serve",
 )
 
 
@@ -47,6 +48,13 @@ class IgsInfo(ctypes.Structure):
         d["last_cycle_status"] = CYCLE_STATUS[self.last_cycle_status] \
             if 0 <= self.last_cycle_status < len(CYCLE_STATUS) else self.last_cycle_status
         return d
+
+
+class IgsRequest(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("nnz", c_int64), ("row_ptr", c_void_p), ("col_idx", c_void_p),
+                ("vals", c_void_p), ("b", c_void_p), ("x", c_void_p), ("arrival", c_double),
+                ("t_admit", c_double), ("t_done", c_double), ("iters", c_int64), ("rc", c_int),
+                ("status", c_int)]
 
 
 class IgsError(RuntimeError):
@@ -82,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "igs_kernel_update": (c_int, [P, P, c_int64, c_int, P, P, P, c_double]),
         "igs_profile_get": (c_int, [P, c_int, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
         "igs_profile_reset": (c_int, [P]),
+        "igs_serve": (c_int, [POINTER(IgsRequest), c_int, c_int, c_int64, c_int, c_double, c_int,
+                              POINTER(IgsOpts), POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -194,3 +204,14 @@ def igs_profile_get(ctx, which):
 
 def igs_profile_reset(ctx) -> None:
     _check("igs_profile_reset", load_library().igs_profile_reset(ctx), ctx)
+
+
+def igs_serve(reqs, slots, mem_cap, restart, tol, gs_iters, opts: IgsOpts | None = None):
+    """reqs: a ctypes array of IgsRequest whose host arrays the caller keeps
+    alive.  Returns (return code, wall seconds); raises on argument errors."""
+    wall = c_double(0.0)
+    rc = load_library().igs_serve(reqs, len(reqs), int(slots), int(mem_cap), int(restart),
+                                  float(tol), int(gs_iters), ctypes.byref(opts) if opts else None,
+                                  ctypes.byref(wall))
+    _check("igs_serve", rc, None)
+    return rc, wall.value

@@ -58,6 +58,8 @@ int main(void) {
          offsetof(igs_opts, keep_first_basis), sizeof(igs_info), offsetof(igs_info, seconds));
   printf("%d %d\n", IGS_MAX_RESTART, IGS_K_COUNT);
   printf("%zu %zu\n", offsetof(igs_opts, inner_fp32), offsetof(igs_opts, inner_rtol));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(igs_request), offsetof(igs_request, arrival),
+         offsetof(igs_request, iters), offsetof(igs_request, rc), offsetof(igs_request, status));
   return 0;
 }
 ''')
@@ -74,6 +76,10 @@ int main(void) {
     from paper_2205_07805_amd import igs
     assert vals[5] == igs.IGS_MAX_RESTART and vals[6] == igs.IGS_K_COUNT
     assert vals[7] == IgsOpts.inner_fp32.offset and vals[8] == IgsOpts.inner_rtol.offset
+    from paper_2205_07805_amd.igs import IgsRequest
+    assert vals[9] == ctypes.sizeof(IgsRequest) and vals[10] == IgsRequest.arrival.offset
+    assert vals[11] == IgsRequest.iters.offset and vals[12] == IgsRequest.rc.offset
+    assert vals[13] == IgsRequest.status.offset
 
 
 def test_missing_library_fails_loudly(tmp_path):
@@ -95,3 +101,25 @@ def test_create_rejects_bad_input_without_gpu_work(lib):
     rc = igs.load_library().igs_create(ctypes.byref(ctx), 0, 0, None, None, None, 0, None)
     assert rc == igs.IGS_EINVAL and not ctx.value
     assert "invalid" in igs.igs_last_error(None)
+
+
+def test_serve_rejects_bad_arguments_without_gpu_work(lib):
+    """igs_serve checks its arguments and every request's size against the
+    memory cap before it touches the device."""
+    import numpy as np
+    from paper_2205_07805_amd import igs
+    L = igs.load_library()
+    reqs = (igs.IgsRequest * 1)()
+    b = np.ones(4)
+    x = np.zeros(4)
+    r = reqs[0]
+    r.n, r.nnz, r.b, r.x = 4, 4, b.ctypes.data, x.ctypes.data
+    assert L.igs_serve(reqs, 1, 0, 1 << 30, 10, 1e-10, 2, None, None) == igs.IGS_EINVAL
+    assert L.igs_serve(reqs, 1, 1, 0, 10, 1e-10, 2, None, None) == igs.IGS_EINVAL
+    assert L.igs_serve(reqs, 1, 1, 1 << 30, 0, 1e-10, 2, None, None) == igs.IGS_EINVAL
+    # 4 rows need a few KiB: a 1 KiB cap admits nothing, so nothing runs
+    assert L.igs_serve(reqs, 1, 1, 1024, 10, 1e-10, 2, None, None) == igs.IGS_EINVAL
+    assert "more than the cap" in igs.igs_last_error(None)
+    assert r.rc == igs.IGS_EINVAL and r.t_admit == -1.0
+    with pytest.raises(igs.IgsError):
+        igs.igs_serve(reqs, 0, 1 << 30, 10, 1e-10, 2)

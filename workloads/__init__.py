@@ -230,3 +230,37 @@ def make_dense_nonnormal(n: int = 4096):
     """Dense non-normal matrix (s from 1 to 1e-10, upper part x1e2), b seed 0."""
     a = dense_nonnormal(n)
     return a, rhs_normal(n, 0)
+
+
+@dataclass(frozen=True)
+class Request:
+    """One request of a serving trace: a 2D convection-diffusion system and
+    the time (seconds after the start) at which it arrives."""
+    rid: int
+    side: int
+    pe: float
+    arrival: float
+    a: Csr
+    b: np.ndarray
+
+
+def serving_trace(count: int = 512, seed: int = 7, side_lo: int = 32, side_hi: int = 512,
+                  pe_lo: float = 1.0, pe_hi: float = 100.0, rate: float = 200.0):
+    """A seeded trace of independent solves of uneven size: grid sides uniform
+    on the integers [side_lo, side_hi] (n = side^2), Pe uniform on [pe_lo,
+    pe_hi], Poisson arrivals at `rate` per second (exponential gaps), and
+    b ~ N(0, 1) seeded by the request id."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_lo, side_hi + 1, size=count)
+    pes = rng.uniform(pe_lo, pe_hi, size=count)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count)) if rate > 0 else np.zeros(count)
+    out = []
+    for i in range(count):
+        a = convdiff2d(int(sides[i]), float(pes[i]))
+        out.append(Request(i, int(sides[i]), float(pes[i]), float(arrivals[i]), a,
+                           rhs_normal(a.n, 1000 + i)))
+    return out
+
+
+SERVING = Workload("serving_convdiff2d_side32-512_Pe1-100_poisson200", restart=50, tol=1e-12,
+                   gs_iters=2)
