@@ -222,6 +222,50 @@ typedef struct igs_request {
 int igs_serve(igs_request *reqs, int nreq, int slots, int64_t mem_cap, int restart,
               double tol, int gs_iters, const igs_opts *opts, double *wall_seconds);
 
+/* ---- Batches: many independent solves advanced by each launch ------------ */
+
+/* Most solves one batch advances together. */
+#define IGS_MAX_BATCH 32
+
+/*
+ * Solve count independent systems A_k x_k = b_k (Section 4, Algorithm 4.2,
+ * as igs_solve_opts) together: every step of the restart cycle (operator
+ * apply, fused reduction, small solve and update, least squares, x update)
+ * is one kernel launch for all members, each member on a contiguous range of
+ * the grid equal to the grid its lone solve launches.  Members may differ in
+ * n and in their operators; a member whose cycle ended waits, at no cost
+ * beyond the launches, until the others end theirs.  Each x_k is
+ * bit-identical to igs_solve_opts(ctxs[k], b[k], x[k], ...) alone.
+ *   ctxs[k]: distinct CSR contexts on one device; the batch runs on the
+ *            stream of ctxs[0] after each member's stream is synchronised.
+ *   b[k], x[k]: device float64[n_k], 16-byte aligned; x[k] holds x0 on entry
+ *            and the solution on return.
+ *   count: 1..IGS_MAX_BATCH.  restart, tol, gs_iters, opts: as
+ *            igs_solve_opts (opts may be NULL).  two_reduce and
+ *            keep_first_basis are not supported here (IGS_ENOTIMPL).
+ *   infos[k] (may be NULL): as igs_solve_opts reports for member k.
+ *   rcs[k] (may be NULL): member k's return code as igs_solve_opts gives it.
+ * Returns IGS_OK when every member converged, IGS_ENOCONV when some did not,
+ * a negative code when a member failed (see rcs) or the call is invalid
+ * (message in igs_last_error(ctxs[0]), or igs_last_error(NULL) when ctxs or
+ * count is invalid).
+ */
+int igs_solve_batch(igs_ctx *const *ctxs, const double *const *b, double *const *x, int count,
+                    int restart, double tol, int gs_iters, const igs_opts *opts,
+                    igs_info *infos, int *rcs);
+
+/*
+ * igs_serve with batched kernels: one stream and up to `batch`
+ * (1..IGS_MAX_BATCH) requests advanced by each launch, as igs_solve_batch.
+ * Admission happens between restart cycles: after every cycle the finished
+ * requests leave (x copied back) and the oldest arrived requests join while a
+ * member is free and the memory cap allows.  Requests, memory accounting,
+ * outputs and return codes are those of igs_serve; each x is bit-identical to
+ * a lone solve.  two_reduce is not supported (IGS_ENOTIMPL).
+ */
+int igs_serve_batched(igs_request *reqs, int nreq, int batch, int64_t mem_cap, int restart,
+                      double tol, int gs_iters, const igs_opts *opts, double *wall_seconds);
+
 /* ---- Inspection of the FIRST restart cycle of the last solve (tests) ----- */
 
 /* Copy the Hessenberg matrix H (before Givens rotation) of the first cycle to

@@ -138,5 +138,54 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
 hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
                              const double* t, const double* r1, double inv_gamma, hipStream_t s);
 
+// ---- batches: many independent solves advanced together --------------------
+//
+// Every launch of a batched step runs the same step for all instances of a
+// batch: instance k gets a contiguous range of the grid (starting at a
+// multiple of 8, so block k mod 8 still names its XCD) and sees it as a grid
+// of its own.  Each instance's grid, and so its summation order, is the one a
+// lone solve of that instance would launch, which keeps every result
+// bit-identical to the lone solve.
+
+constexpr int kMaxBatch = 32;
+
+// One instance of a batch (device table, written by the host once per cycle).
+struct Inst {
+  Work w;              // its workspace and control block
+  Op op;               // its CSR operator
+  long long n;
+  const double* b;
+  double* x;
+  long long its_before;  // iterations finished before this cycle
+  long long maxit;       // iteration budget of this cycle
+  double tol, tau, cycle_rtol;
+  int m, gs, final_v;
+  int run_lsq;           // 0: the cycle is a final check (iteration 0 only)
+};
+
+// Host view of a batch for one launch: the instances taking part.
+struct BatchRun {
+  const Inst* d_tab;   // device table
+  const Inst* h_tab;   // its host copy (sizes and operators)
+  int act[kMaxBatch];  // table rows taking part
+  int count;
+  hipStream_t stream;
+};
+
+// ||b|| and the finiteness check of the instances act[0..count).
+hipError_t batch_bnorm(const BatchRun& r);
+// Cycle start: reset each control block, then r = b - A x into column 0.
+hipError_t batch_residual(const BatchRun& r);
+// z = A u_j for every instance (skipped per instance once its cycle ended).
+hipError_t batch_spmv(const BatchRun& r, int j);
+// The fused reduction of iteration j; ngroups[k] receives the group count
+// of instance act[k] for the update.
+hipError_t batch_reduce(const BatchRun& r, int j, bool with_z, int* ngroups);
+hipError_t batch_update(const BatchRun& r, int j, const int* ngroups);
+// R y = g and x += V y for the instances with run_lsq.
+hipError_t batch_lsq(const BatchRun& r, int m);
+hipError_t batch_xupdate(const BatchRun& r);
+// Copy each instance's control block to out[act[k]] (device memory).
+hipError_t batch_ctl_gather(const BatchRun& r, Ctl* out);
 
 }  // namespace igs

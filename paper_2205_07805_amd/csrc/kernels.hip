@@ -128,6 +128,15 @@ __device__ __forceinline__ int load_agent(const int* p) {
 // Does iteration j of the current cycle run (the cycle has not ended before it)?
 __device__ __forceinline__ bool ctl_runs(const Ctl* c, int j) { return load_agent(&c->end_iter) >= j; }
 
+// The blocks of one operation as its code sees them: block `bid` of `nb`.
+// A kernel that runs one instance uses (blockIdx.x, gridDim.x); a batched
+// kernel gives each instance a contiguous range of its grid.
+struct Grid {
+  int bid;
+  int nb;
+};
+__device__ __forceinline__ Grid hw_grid() { return Grid{(int)blockIdx.x, (int)gridDim.x}; }
+
 // Blocks are dispatched round-robin over the 8 XCDs.  Give each XCD a
 // contiguous range of logical blocks so that the neighbour gathers of the
 // operator apply hit the L2 of that XCD.
@@ -173,11 +182,11 @@ __device__ void sum_rows(const double* src, int pstride, int cnt, int nv, double
 
 // Deterministic sums of nv per-block values, in two levels.
 // Precondition: wave 0 of every block has written its block's values to
-// part[blockIdx.x * pstride + v], v < nv (only wave 0 writes, so that its one
+// part[bid * pstride + v], v < nv (only wave 0 writes, so that its one
 // release fence publishes all of them).
 //
 // First level (group_reduce_last): the blocks are split into up to 8 groups
-// by blockIdx % 8 -- the blocks of one group then run on one XCD under the
+// by bid % 8 -- the blocks of one group then run on one XCD under the
 // hardware's round-robin dispatch, so a group's partials and its counter stay
 // in one L2 (the result does not depend on where blocks run) -- and the last
 // block of a group to arrive sums that group in a fixed order into gpart[g]
@@ -185,11 +194,11 @@ __device__ void sum_rows(const double* src, int pstride, int cnt, int nv, double
 // (shared memory) holding the group's totals.  scratch: shared memory of
 // max(blockDim.x, nv) doubles, disjoint from out.
 __device__ bool group_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
-                                  int nv, double* out, double* scratch) {
+                                  int nv, double* out, double* scratch, Grid gr) {
   __shared__ int s_last;
-  const int nb = gridDim.x;
+  const int nb = gr.nb;
   const int ngroups = nb < 8 ? nb : 8;
-  const int g = blockIdx.x % ngroups;
+  const int g = gr.bid % ngroups;
   const int gsize = (nb - g + ngroups - 1) / ngroups;
   if (threadIdx.x < kWave) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -210,10 +219,10 @@ __device__ bool group_reduce_last(double* part, double* gpart, int pstride, unsi
 // Both levels: the last group to finish sums the group totals.  Returns true
 // in exactly one block; there out[v] holds the grid totals.
 __device__ bool grid_reduce_last(double* part, double* gpart, int pstride, unsigned* tickets,
-                                 int nv, double* out, double* scratch) {
+                                 int nv, double* out, double* scratch, Grid gr) {
   __shared__ int s_last;
-  if (!group_reduce_last(part, gpart, pstride, tickets, nv, out, scratch)) return false;
-  const int ngroups = reduce_groups(gridDim.x);
+  if (!group_reduce_last(part, gpart, pstride, tickets, nv, out, scratch, gr)) return false;
+  const int ngroups = reduce_groups(gr.nb);
   if (threadIdx.x < kWave) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (threadIdx.x == 0) s_last = (atomicAdd(&tickets[kMaxGroups], 1u) == (unsigned)(ngroups - 1));
@@ -248,18 +257,17 @@ __device__ __forceinline__ double wave_dot(const double* a, const double* b, int
 // rows.  Rows longer than LPR finish in a strided loop.
 // TA: type of the matrix values, x, bsub and the sums; TY: type of y.
 template <int LPR, int RPG, typename TA, typename TY>
-__global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* __restrict__ rp,
-                                                       const int* __restrict__ ci,
-                                                       const TA* __restrict__ va,
-                                                       const TA* __restrict__ x,
-                                                       TY* __restrict__ y,
-                                                       const TA* __restrict__ bsub,
-                                                       const Ctl* __restrict__ gate, int gate_j) {
+__device__ __forceinline__ void spmv_csr_body(Grid gr, long long n, const int* __restrict__ rp,
+                                              const int* __restrict__ ci,
+                                              const TA* __restrict__ va,
+                                              const TA* __restrict__ x, TY* __restrict__ y,
+                                              const TA* __restrict__ bsub,
+                                              const Ctl* __restrict__ gate, int gate_j) {
   constexpr int G = kWave / LPR;
   // the gate is read together with the row bounds, so its latency overlaps
   // theirs; nothing is stored before it is checked
   const int act = (gate != nullptr) ? (load_agent(&gate->end_iter) >= gate_j) : 1;
-  const long long lb = xcd_block(blockIdx.x, gridDim.x);
+  const long long lb = xcd_block(gr.bid, gr.nb);
   const long long wv = (lb * blockDim.x + threadIdx.x) / kWave;
   const int g = (int)(threadIdx.x % kWave) / LPR;
   const int lane = threadIdx.x % LPR;
@@ -306,6 +314,17 @@ __global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* _
   }
 }
 
+template <int LPR, int RPG, typename TA, typename TY>
+__global__ __launch_bounds__(256) void spmv_csr_kernel(long long n, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci,
+                                                       const TA* __restrict__ va,
+                                                       const TA* __restrict__ x,
+                                                       TY* __restrict__ y,
+                                                       const TA* __restrict__ bsub,
+                                                       const Ctl* __restrict__ gate, int gate_j) {
+  spmv_csr_body<LPR, RPG, TA, TY>(hw_grid(), n, rp, ci, va, x, y, bsub, gate, gate_j);
+}
+
 // Dense row-major operator: one wave per row, 16-byte loads.
 __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const double* __restrict__ A,
                                                          long long lda,
@@ -332,9 +351,22 @@ __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const doub
   if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
 }
 
-template <typename TA> const TA* op_vals(const Op& op);
-template <> const double* op_vals<double>(const Op& op) { return op.vals; }
-template <> const float* op_vals<float>(const Op& op) { return op.vals32; }
+template <typename TA> __host__ __device__ const TA* op_vals(const Op& op);
+template <> __host__ __device__ const double* op_vals<double>(const Op& op) { return op.vals; }
+template <> __host__ __device__ const float* op_vals<float>(const Op& op) { return op.vals32; }
+
+// Lanes per row LPR (a power of two near the mean row length) and rows per
+// lane group RPG: up to 4 rows while a group is at most 8 lanes wide.
+static int spmv_rpg(int lpr) { return lpr <= 8 ? (LPR_RPG_MAX) : (lpr == 16 ? 2 : 1); }
+
+static unsigned spmv_grid(long long n, int lpr) {
+  const int rpg = spmv_rpg(lpr);
+  const long long groups = (n + rpg - 1) / rpg;
+  const long long threads = groups * lpr;
+  unsigned grid = (unsigned)((threads + 255) / 256);
+  if (grid >= 64) grid = (grid + 7) / 8 * 8;  // multiple of 8 for the XCD mapping
+  return grid;
+}
 
 template <typename TA, typename TY>
 static hipError_t op_apply(const Op& op, const TA* x, TY* y, const TA* bsub, const Ctl* gate,
@@ -352,14 +384,8 @@ static hipError_t op_apply(const Op& op, const TA* x, TY* y, const TA* bsub, con
   }
   const TA* vals = op_vals<TA>(op);
   if (vals == nullptr) return hipErrorInvalidValue;
-  // lanes per row LPR (a power of two near the mean row length), rows per lane
-  // group RPG: up to 4 rows while a group is at most 8 lanes wide
   const int lpr = op.lpr;
-  const int rpg = lpr <= 8 ? (LPR_RPG_MAX) : (lpr == 16 ? 2 : 1);
-  const long long groups = (op.n + rpg - 1) / rpg;
-  const long long threads = groups * lpr;
-  unsigned grid = (unsigned)((threads + 255) / 256);
-  if (grid >= 64) grid = (grid + 7) / 8 * 8;  // multiple of 8 for the XCD mapping
+  const unsigned grid = spmv_grid(op.n, lpr);
   switch (lpr) {
 #define IGS_SPMV_CASE(L, R)                                                                     \
   case L:                                                                                       \
@@ -406,9 +432,9 @@ hipError_t launch_round_to_float(const double* src, float* dst, long long count,
 // cycle start: reset the control block, then r0 = b - A x into V[:, 0]
 // ---------------------------------------------------------------------------
 
-__global__ void cycle_begin_kernel(Ctl* c, long long its_before, long long maxit, int m, int gs,
-                                   int final_v, double tol, double tau, double cycle_rtol) {
-  if (threadIdx.x != 0) return;
+__device__ __forceinline__ void cycle_begin_body(Ctl* c, long long its_before, long long maxit,
+                                                 int m, int gs, int final_v, double tol,
+                                                 double tau, double cycle_rtol) {
   c->end_iter = kNotEnded;
   c->J = 0;
   c->status = kRunning;
@@ -427,6 +453,12 @@ __global__ void cycle_begin_kernel(Ctl* c, long long its_before, long long maxit
   c->gabs = 0.0;
 }
 
+__global__ void cycle_begin_kernel(Ctl* c, long long its_before, long long maxit, int m, int gs,
+                                   int final_v, double tol, double tau, double cycle_rtol) {
+  if (threadIdx.x != 0) return;
+  cycle_begin_body(c, its_before, maxit, m, gs, final_v, tol, tau, cycle_rtol);
+}
+
 hipError_t launch_residual(const Op& op, const double* b, const double* x, const Work& w,
                            long long its_before, long long maxit, int m, int gs, int final_v,
                            double tol, double tau, double cycle_rtol, hipStream_t s) {
@@ -442,15 +474,15 @@ hipError_t launch_residual(const Op& op, const double* b, const double* x, const
 // ||b|| and a finiteness check of b and x0 (once per solve)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void bnorm_kernel(const double* __restrict__ b,
-                                                    const double* __restrict__ x, long long n,
-                                                    Work w) {
+__device__ __forceinline__ void bnorm_body(Grid gr, const double* __restrict__ b,
+                                           const double* __restrict__ x, long long n,
+                                           const Work& w) {
   __shared__ double red[2][256 / kWave];
   __shared__ double tot[2];
   __shared__ double scr[256];
   double s2 = 0.0, bad = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
+  for (long long i = (long long)gr.bid * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gr.nb * blockDim.x) {
     const double bi = b[i];
     const double xi = x[i];
     s2 = fma(bi, bi, s2);
@@ -467,15 +499,21 @@ __global__ __launch_bounds__(256) void bnorm_kernel(const double* __restrict__ b
   if (threadIdx.x < 2) {
     double acc = 0.0;
     for (int k = 0; k < (int)(blockDim.x / kWave); ++k) acc += red[threadIdx.x][k];
-    w.part[(size_t)blockIdx.x * w.pstride + threadIdx.x] = acc;
+    w.part[(size_t)gr.bid * w.pstride + threadIdx.x] = acc;
   }
-  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2, tot, scr)) return;
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2, tot, scr, gr)) return;
   if (threadIdx.x == 0) {
     w.ctl->bnorm = sqrt(tot[0]);
     w.ctl->nonfinite_in = (int)tot[1];
     w.ctl->breakdowns = 0;
     w.ctl->fallbacks = 0;
   }
+}
+
+__global__ __launch_bounds__(256) void bnorm_kernel(const double* __restrict__ b,
+                                                    const double* __restrict__ x, long long n,
+                                                    Work w) {
+  bnorm_body(hw_grid(), b, x, n, w);
 }
 
 hipError_t launch_bnorm(const double* b, const double* x, long long n, const Work& w,
@@ -1167,8 +1205,8 @@ template <> __host__ __device__ double* zvec<double>(const Work& w) { return w.z
 template <> __host__ __device__ float* zvec<float>(const Work& w) { return w.z32; }
 
 template <int CPW, bool VEC, bool Z, typename T>
-__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
-    Work w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr,
+__device__ __forceinline__ void reduce_body(
+    Grid gr, const Work& w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr,
     const T* __restrict__ Vraw, long long ldv_raw, const T* __restrict__ zraw,
     double* __restrict__ raw_out) {
   extern __shared__ double lds[];
@@ -1180,7 +1218,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
   const int ncol = j + 1;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const long long r0 = (long long)blockIdx.x * rows_per_block;
+  const long long r0 = (long long)gr.bid * rows_per_block;
   const long long r1 = min(n, r0 + rows_per_block);
   const T* __restrict__ u = V + (size_t)j * ldv;
   const int nchunk = (ncol + cpw - 1) / cpw;
@@ -1211,7 +1249,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
   __syncthreads();
   // the block's partial sums, written by wave 0 only (see grid_reduce_last)
   if (wave == 0) {
-    double* part = w.part + (size_t)blockIdx.x * w.pstride;
+    double* part = w.part + (size_t)gr.bid * w.pstride;
     for (int v = lane; v < 2 * ncol; v += kWave) {
       double acc = 0.0;
       for (int k = 0; k < wr; ++k) acc += lds[(size_t)k * 2 * ncol + v];
@@ -1221,12 +1259,21 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
   if (!raw) {
     // The group totals stay in w.gpart: every block of this iteration's
     // update kernel sums them and runs the small solve itself.
-    group_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol);
+    group_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol, gr);
     return;
   }
-  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol))
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 2 * ncol, lds, lds + 2 * ncol, gr))
     return;
   for (int v = threadIdx.x; v < 2 * ncol; v += blockDim.x) raw_out[v] = lds[v];
+}
+
+template <int CPW, bool VEC, bool Z, typename T>
+__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
+    Work w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr,
+    const T* __restrict__ Vraw, long long ldv_raw, const T* __restrict__ zraw,
+    double* __restrict__ raw_out) {
+  reduce_body<CPW, VEC, Z, T>(hw_grid(), w, n, j, rows_per_block, cpw, wc, wr, Vraw, ldv_raw, zraw,
+                              raw_out);
 }
 
 // Shared memory of the fused reduction: the wave partials; then the totals
@@ -1378,9 +1425,9 @@ __device__ void correct_coefs(const Work& w, int j, const double* P, double* sm,
 }
 
 template <bool HAS_T, bool VEC, typename T>
-__global__ __launch_bounds__(kUpdateThreads) void update_kernel(
-    Work w, long long n, int j, int ngroups, T* __restrict__ Vraw, long long ldv_raw,
-    const T* __restrict__ zraw, const double* __restrict__ traw,
+__device__ __forceinline__ void update_body(
+    Grid gr, const Work& w, long long n, int j, int ngroups, T* __restrict__ Vraw,
+    long long ldv_raw, const T* __restrict__ zraw, const double* __restrict__ traw,
     const double* __restrict__ r1raw, double igraw, int raw) {
   // raw: 1 = step kernel on caller buffers, 2 = two-reduce second sweep
   typedef typename Vec16<T>::type VT;
@@ -1424,7 +1471,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
       sdyn[v] = acc;
     }
     __syncthreads();
-    const bool pub = (blockIdx.x == 0);
+    const bool pub = (gr.bid == 0);
     if (raw == 2) {
       correct_coefs(w, j, sP, sm, pub);
       mode = kUpdCorrect;
@@ -1447,7 +1494,7 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   constexpr long long kTile = update_tile_rows<T>();
   const long long ntiles = (n + kTile - 1) / kTile;
   double s2 = 0.0;  // ||w||^2 partial (fallback only)
-  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
     if constexpr (VEC) {
       // Full tile: the thread owns the row vectors at p0 = W t and
       // p1 = p0 + W kUpdateThreads; V is streamed with 16-byte non-temporal
@@ -1613,9 +1660,10 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
   if (threadIdx.x == 0) {
     double acc = 0.0;
     for (int k = 0; k < kUpdateThreads / kWave; ++k) acc += red[k];
-    w.part[(size_t)blockIdx.x * w.pstride] = acc;
+    w.part[(size_t)gr.bid * w.pstride] = acc;
   }
-  if (!grid_reduce_last(w.part, w.gpart + (size_t)8 * w.pstride, w.pstride, w.tickets, 1, tot, scr))
+  if (!grid_reduce_last(w.part, w.gpart + (size_t)8 * w.pstride, w.pstride, w.tickets, 1, tot, scr,
+                        gr))
     return;
   const double gamma = sqrt(tot[0]);
   // scratch in shared memory: the column (as the publisher stored it), the
@@ -1647,6 +1695,15 @@ __global__ __launch_bounds__(kUpdateThreads) void update_kernel(
     }
     c->mode = kUpdNone;
   }
+}
+
+template <bool HAS_T, bool VEC, typename T>
+__global__ __launch_bounds__(kUpdateThreads) void update_kernel(
+    Work w, long long n, int j, int ngroups, T* __restrict__ Vraw, long long ldv_raw,
+    const T* __restrict__ zraw, const double* __restrict__ traw,
+    const double* __restrict__ r1raw, double igraw, int raw) {
+  update_body<HAS_T, VEC, T>(hw_grid(), w, n, j, ngroups, Vraw, ldv_raw, zraw, traw, r1raw, igraw,
+                             raw);
 }
 
 // Tiles of update_tile_rows<T>() rows, one round of resident blocks striding
@@ -1735,7 +1792,7 @@ static int lsq_panel(int m) {
   return p;
 }
 
-__global__ __launch_bounds__(256) void lsq_kernel(Work w, int panel) {
+__device__ __forceinline__ void lsq_body(const Work& w, int panel) {
   extern __shared__ double sm[];
   const int J = load_agent(&w.ctl->J);
   if (J <= 0) return;
@@ -1766,6 +1823,8 @@ __global__ __launch_bounds__(256) void lsq_kernel(Work w, int panel) {
   }
 }
 
+__global__ __launch_bounds__(256) void lsq_kernel(Work w, int panel) { lsq_body(w, panel); }
+
 hipError_t launch_lsq(const Work& w, int m, hipStream_t s) {
   const int panel = lsq_panel(m);
   const size_t lds = ((size_t)m + 1 + (size_t)panel * m) * sizeof(double);
@@ -1775,15 +1834,15 @@ hipError_t launch_lsq(const Work& w, int m, hipStream_t s) {
 
 // x += V_{0:J} y (x and y FP64; V in the basis element type T).
 template <typename T>
-__global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long long n,
-                                                                double* __restrict__ x) {
+__device__ __forceinline__ void xupdate_body(Grid gr, const Work& w, long long n,
+                                             double* __restrict__ x) {
   const int J = load_agent(&w.ctl->J);
   if (J <= 0) return;
   const double* __restrict__ y = w.y;
   const T* __restrict__ V = basis<T>(w);
   constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
   const long long ntiles = (n + kTile - 1) / kTile;
-  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
     const long long base = tile * kTile + threadIdx.x;
     double acc[kUpdateRows];
 #pragma unroll
@@ -1823,6 +1882,12 @@ __global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long lo
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long long n,
+                                                                double* __restrict__ x) {
+  xupdate_body<T>(hw_grid(), w, n, x);
+}
+
 hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s) {
   const long long per = (long long)kUpdateThreads * kUpdateRows;
   long long g = (n + per - 1) / per;
@@ -1834,6 +1899,360 @@ hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s) 
     hipLaunchKernelGGL(xupdate_kernel<double>, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w,
                        n, x);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batches: one launch runs the same step for many independent instances
+// ---------------------------------------------------------------------------
+
+// Instance k of a launch owns blocks [start, start + nblk) of the grid
+// (start a multiple of 8); aux carries a per-instance launch parameter.
+struct MapEntry {
+  int start;
+  int nblk;
+  int inst;
+  int pad;
+  long long aux;
+};
+struct BatchMap {
+  int count;
+  int total;
+  MapEntry e[kMaxBatch];
+};
+
+// The entry that owns this block: a scan over compile-time indices of the
+// kernel argument (no dynamic indexing into it).
+__device__ __forceinline__ MapEntry map_find(const BatchMap& m) {
+  MapEntry r = m.e[0];
+#pragma unroll
+  for (int k = 1; k < kMaxBatch; ++k)
+    if (k < m.count && (int)blockIdx.x >= m.e[k].start) r = m.e[k];
+  return r;
+}
+
+template <int LPR, int RPG, typename T, bool RESID>
+__global__ __launch_bounds__(256) void spmv_batch_kernel(const Inst* __restrict__ tab,
+                                                         BatchMap map, int j) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  const Inst I = tab[e.inst];
+  const Grid gr{bid, e.nblk};
+  if constexpr (RESID) {
+    // r = b - A x in FP64, stored in the basis element type
+    spmv_csr_body<LPR, RPG, double, T>(gr, I.n, I.op.row_ptr, I.op.col_idx, I.op.vals, I.x,
+                                       basis<T>(I.w), I.b, nullptr, 0);
+  } else {
+    spmv_csr_body<LPR, RPG, T, T>(gr, I.n, I.op.row_ptr, I.op.col_idx, op_vals<T>(I.op),
+                                  basis<T>(I.w) + (size_t)j * I.w.ldv, zvec<T>(I.w), nullptr,
+                                  I.w.ctl, j);
+  }
+}
+
+template <int CPW, bool VEC, bool Z, typename T>
+__global__ __launch_bounds__(kReduceThreads) void reduce_batch_kernel(const Inst* __restrict__ tab,
+                                                                      BatchMap map, int j, int cpw,
+                                                                      int wc, int wr) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  // copies taken before any store, so that they load through the scalar
+  // path and live in scalar registers as kernel arguments would
+  const Work w = tab[e.inst].w;
+  const long long n = tab[e.inst].n;
+  reduce_body<CPW, VEC, Z, T>(Grid{bid, e.nblk}, w, n, j, e.aux, cpw, wc, wr, nullptr, 0, nullptr,
+                              nullptr);
+}
+
+template <bool HAS_T, bool VEC, typename T>
+__global__ __launch_bounds__(kUpdateThreads) void update_batch_kernel(const Inst* __restrict__ tab,
+                                                                      BatchMap map, int j) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  const Work w = tab[e.inst].w;
+  const long long n = tab[e.inst].n;
+  update_body<HAS_T, VEC, T>(Grid{bid, e.nblk}, w, n, j, (int)e.aux, nullptr, 0, nullptr, nullptr,
+                             nullptr, 0.0, 0);
+}
+
+__global__ __launch_bounds__(256) void bnorm_batch_kernel(const Inst* __restrict__ tab,
+                                                          BatchMap map) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  const Inst I = tab[e.inst];
+  bnorm_body(Grid{bid, e.nblk}, I.b, I.x, I.n, I.w);
+}
+
+__global__ void cycle_begin_batch_kernel(const Inst* __restrict__ tab, BatchMap map) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk || threadIdx.x != 0) return;
+  const Inst& I = tab[e.inst];
+  cycle_begin_body(I.w.ctl, I.its_before, I.maxit, I.m, I.gs, I.final_v, I.tol, I.tau,
+                   I.cycle_rtol);
+}
+
+__global__ __launch_bounds__(256) void lsq_batch_kernel(const Inst* __restrict__ tab, BatchMap map,
+                                                        int panel) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  const Work w = tab[e.inst].w;
+  if (!tab[e.inst].run_lsq) return;
+  lsq_body(w, panel);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kUpdateThreads) void xupdate_batch_kernel(const Inst* __restrict__ tab,
+                                                                       BatchMap map) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  const Inst I = tab[e.inst];
+  if (!I.run_lsq) return;
+  xupdate_body<T>(Grid{bid, e.nblk}, I.w, I.n, I.x);
+}
+
+__global__ void ctl_gather_kernel(const Inst* __restrict__ tab, BatchMap map, Ctl* out) {
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  const int* src = reinterpret_cast<const int*>(tab[e.inst].w.ctl);
+  int* dst = reinterpret_cast<int*>(out + e.inst);
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int)); i += blockDim.x) dst[i] = src[i];
+}
+
+// Lay out the instances act[k] of a launch with nblk[k] blocks each.
+static void build_map(BatchMap& m, const BatchRun& r, const int* nblk, const long long* aux) {
+  m.count = r.count;
+  int start = 0;
+  for (int k = 0; k < r.count; ++k) {
+    m.e[k] = MapEntry{start, nblk[k], r.act[k], 0, aux ? aux[k] : 0};
+    start += (nblk[k] + 7) / 8 * 8;
+  }
+  for (int k = r.count; k < kMaxBatch; ++k) m.e[k] = MapEntry{start, 0, 0, 0, 0};
+  m.total = start;
+}
+
+static bool batch_fp32(const BatchRun& r) { return r.h_tab[r.act[0]].w.fp32 != 0; }
+
+// 16-byte row vectors for every instance (whole vectors per column, aligned
+// columns); the batch kernels have no element path for other layouts.
+template <typename T>
+static bool batch_vec(const BatchRun& r) {
+  for (int k = 0; k < r.count; ++k) {
+    const Work& w = r.h_tab[r.act[k]].w;
+    if (w.ldv % Vec16<T>::W != 0 || reinterpret_cast<uintptr_t>(basis<T>(w)) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(zvec<T>(w)) % 16 != 0)
+      return false;
+  }
+  return true;
+}
+
+static hipError_t launch_map(const void* kernel, const BatchMap& m, unsigned threads, size_t lds,
+                             void** args, hipStream_t s) {
+  if (m.total == 0) return hipSuccess;
+  return hipLaunchKernel(kernel, dim3((unsigned)m.total), dim3(threads), args, lds, s);
+}
+
+hipError_t batch_bnorm(const BatchRun& r) {
+  if (r.count <= 0) return hipSuccess;
+  int nb[kMaxBatch];
+  for (int k = 0; k < r.count; ++k) {
+    long long blocks = (r.h_tab[r.act[k]].n + 255) / 256;   // as launch_bnorm
+    nb[k] = (int)(blocks > 1024 ? 1024 : blocks);
+  }
+  BatchMap m;
+  build_map(m, r, nb, nullptr);
+  const Inst* t = r.d_tab;
+  void* args[] = {&t, &m};
+  return launch_map(reinterpret_cast<const void*>(bnorm_batch_kernel), m, 256, 0, args, r.stream);
+}
+
+// The operator apply for the instances with lanes-per-row `lpr` (one launch
+// per distinct value; RESID: the residual r = b - A x of the cycle start).
+template <typename T, bool RESID>
+static hipError_t batch_spmv_lpr(const BatchRun& r, int j) {
+  bool seen[7] = {false, false, false, false, false, false, false};
+  for (int k = 0; k < r.count; ++k) {
+    const int lpr = r.h_tab[r.act[k]].op.lpr;
+    int li = 0;
+    while ((1 << li) < lpr) ++li;
+    if ((1 << li) != lpr || li > 6) return hipErrorInvalidValue;
+    if (seen[li]) continue;
+    seen[li] = true;
+    BatchRun sub = r;
+    sub.count = 0;
+    int nb[kMaxBatch];
+    for (int q = 0; q < r.count; ++q) {
+      const Inst& I = r.h_tab[r.act[q]];
+      if (I.op.lpr != lpr) continue;
+      nb[sub.count] = (int)spmv_grid(I.n, lpr);
+      sub.act[sub.count++] = r.act[q];
+    }
+    BatchMap m;
+    build_map(m, sub, nb, nullptr);
+    const Inst* t = r.d_tab;
+    int ja = j;
+    void* args[] = {&t, &m, &ja};
+    const void* kern = nullptr;
+    switch (lpr) {
+#define IGS_BSPMV_CASE(L, R) \
+  case L: kern = reinterpret_cast<const void*>(spmv_batch_kernel<L, R, T, RESID>); break;
+      IGS_BSPMV_CASE(1, LPR_RPG_MAX) IGS_BSPMV_CASE(2, LPR_RPG_MAX) IGS_BSPMV_CASE(4, LPR_RPG_MAX)
+      IGS_BSPMV_CASE(8, LPR_RPG_MAX) IGS_BSPMV_CASE(16, 2) IGS_BSPMV_CASE(32, 1)
+      IGS_BSPMV_CASE(64, 1)
+#undef IGS_BSPMV_CASE
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t err = launch_map(kern, m, 256, 0, args, r.stream);
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t batch_residual(const BatchRun& r) {
+  if (r.count <= 0) return hipSuccess;
+  int nb[kMaxBatch];
+  for (int k = 0; k < r.count; ++k) nb[k] = 1;
+  BatchMap m;
+  build_map(m, r, nb, nullptr);
+  const Inst* t = r.d_tab;
+  void* args[] = {&t, &m};
+  hipError_t e =
+      launch_map(reinterpret_cast<const void*>(cycle_begin_batch_kernel), m, 64, 0, args, r.stream);
+  if (e != hipSuccess) return e;
+  return batch_fp32(r) ? batch_spmv_lpr<float, true>(r, 0) : batch_spmv_lpr<double, true>(r, 0);
+}
+
+hipError_t batch_spmv(const BatchRun& r, int j) {
+  if (r.count <= 0) return hipSuccess;
+  return batch_fp32(r) ? batch_spmv_lpr<float, false>(r, j) : batch_spmv_lpr<double, false>(r, j);
+}
+
+template <typename T>
+static const void* pick_reduce_batch(int tcpw, bool z) {
+  switch (tcpw * 2 + (z ? 1 : 0)) {
+#define IGS_BRED_CASE(C, ZZ) \
+  case C * 2 + ZZ: return reinterpret_cast<const void*>(reduce_batch_kernel<C, true, ZZ, T>);
+    IGS_BRED_CASE(1, 0) IGS_BRED_CASE(1, 1) IGS_BRED_CASE(2, 0) IGS_BRED_CASE(2, 1)
+    IGS_BRED_CASE(4, 0) IGS_BRED_CASE(4, 1) IGS_BRED_CASE(8, 0) IGS_BRED_CASE(8, 1)
+#undef IGS_BRED_CASE
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+static hipError_t batch_reduce_t(const BatchRun& r, int j, bool with_z, int* ngroups) {
+  const int ncol = j + 1;
+  const ReduceShape sh0 = reduce_columns(ncol);
+  const size_t lds = reduce_lds_bytes(sh0, ncol);
+  if (!batch_vec<T>(r)) return hipErrorInvalidValue;
+  const void* kern = pick_reduce_batch<T>(sh0.tcpw, with_z);
+  if (kern == nullptr) return hipErrorInvalidValue;
+  // each instance's grid is the one reduce_dispatch launches for it alone
+  int cap = resident_blocks(reinterpret_cast<const void*>(pick_reduce<T>(sh0.tcpw, true, true)),
+                            kReduceThreads, lds);
+  if (cap > kMaxBlocks) cap = kMaxBlocks;
+  if (sh0.tcpw <= 2) {
+    const int cus = resident_blocks(nullptr, 0, 0);
+    if (cap > cus) cap = cus;
+  }
+  int nb[kMaxBatch];
+  long long rpb[kMaxBatch];
+  for (int k = 0; k < r.count; ++k) {
+    ReduceShape sh = sh0;
+    reduce_rows(sh, r.h_tab[r.act[k]].n, cap);
+    nb[k] = sh.nblocks;
+    rpb[k] = sh.rows_per_block;
+    ngroups[k] = reduce_groups(sh.nblocks);
+  }
+  BatchMap m;
+  build_map(m, r, nb, rpb);
+  const Inst* t = r.d_tab;
+  int ja = j, cpw = sh0.cpw, wc = sh0.wc, wr = sh0.wr;
+  void* args[] = {&t, &m, &ja, &cpw, &wc, &wr};
+  return launch_map(kern, m, kReduceThreads, lds, args, r.stream);
+}
+
+hipError_t batch_reduce(const BatchRun& r, int j, bool with_z, int* ngroups) {
+  if (r.count <= 0) return hipSuccess;
+  return batch_fp32(r) ? batch_reduce_t<float>(r, j, with_z, ngroups)
+                       : batch_reduce_t<double>(r, j, with_z, ngroups);
+}
+
+template <typename T>
+static hipError_t batch_update_t(const BatchRun& r, int j, const int* ngroups) {
+  if (!batch_vec<T>(r)) return hipErrorInvalidValue;
+  const bool has_t = r.h_tab[r.act[0]].gs == 2;
+  const void* kern = has_t ? reinterpret_cast<const void*>(update_batch_kernel<true, true, T>)
+                           : reinterpret_cast<const void*>(update_batch_kernel<false, true, T>);
+  const void* lone = has_t ? reinterpret_cast<const void*>(update_kernel<true, true, T>)
+                           : reinterpret_cast<const void*>(update_kernel<false, true, T>);
+  const size_t lds = update_lds_doubles(j) * sizeof(double);
+  int nb[kMaxBatch];
+  long long ng[kMaxBatch];
+  for (int k = 0; k < r.count; ++k) {
+    nb[k] = (int)update_grid(lone, r.h_tab[r.act[k]].n, update_tile_rows<T>(), lds);
+    ng[k] = ngroups[k];
+  }
+  BatchMap m;
+  build_map(m, r, nb, ng);
+  const Inst* t = r.d_tab;
+  int ja = j;
+  void* args[] = {&t, &m, &ja};
+  return launch_map(kern, m, kUpdateThreads, lds, args, r.stream);
+}
+
+hipError_t batch_update(const BatchRun& r, int j, const int* ngroups) {
+  if (r.count <= 0) return hipSuccess;
+  return batch_fp32(r) ? batch_update_t<float>(r, j, ngroups)
+                       : batch_update_t<double>(r, j, ngroups);
+}
+
+hipError_t batch_lsq(const BatchRun& r, int m) {
+  if (r.count <= 0) return hipSuccess;
+  const int panel = lsq_panel(m);
+  const size_t lds = ((size_t)m + 1 + (size_t)panel * m) * sizeof(double);
+  int nb[kMaxBatch];
+  for (int k = 0; k < r.count; ++k) nb[k] = 1;
+  BatchMap mp;
+  build_map(mp, r, nb, nullptr);
+  const Inst* t = r.d_tab;
+  int pa = panel;
+  void* args[] = {&t, &mp, &pa};
+  return launch_map(reinterpret_cast<const void*>(lsq_batch_kernel), mp, 256, lds, args, r.stream);
+}
+
+hipError_t batch_xupdate(const BatchRun& r) {
+  if (r.count <= 0) return hipSuccess;
+  const long long per = (long long)kUpdateThreads * kUpdateRows;
+  int nb[kMaxBatch];
+  for (int k = 0; k < r.count; ++k) {
+    long long g = (r.h_tab[r.act[k]].n + per - 1) / per;   // as launch_xupdate
+    nb[k] = (int)(g > kMaxBlocks ? kMaxBlocks : g);
+  }
+  BatchMap m;
+  build_map(m, r, nb, nullptr);
+  const Inst* t = r.d_tab;
+  void* args[] = {&t, &m};
+  const void* kern = batch_fp32(r) ? reinterpret_cast<const void*>(xupdate_batch_kernel<float>)
+                                   : reinterpret_cast<const void*>(xupdate_batch_kernel<double>);
+  return launch_map(kern, m, kUpdateThreads, 0, args, r.stream);
+}
+
+hipError_t batch_ctl_gather(const BatchRun& r, Ctl* out) {
+  if (r.count <= 0) return hipSuccess;
+  int nb[kMaxBatch];
+  for (int k = 0; k < r.count; ++k) nb[k] = 1;
+  BatchMap m;
+  build_map(m, r, nb, nullptr);
+  const Inst* t = r.d_tab;
+  Ctl* o = out;
+  void* args[] = {&t, &m, &o};
+  return launch_map(reinterpret_cast<const void*>(ctl_gather_kernel), m, 64, 0, args, r.stream);
 }
 
 }  // namespace igs

@@ -794,18 +794,26 @@ long long request_bytes(long long n, long long nnz, int m, bool fp32) {
 
 // A serving slot: a context with device capacity for CSR operators of up to
 // n_cap rows and nnz_cap entries at restart m, plus b and x, on its own
-// stream.  Requests are bound to it one at a time, so the serving loop
-// allocates and frees no device memory (a free would wait for every stream).
+// stream (or a shared one).  Requests are bound to it one at a time, so the
+// serving loop allocates and frees no device memory (a free would wait for
+// every stream).
 struct Slot {
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   igs_ctx* ctx = nullptr;
   double* b = nullptr;
   double* x = nullptr;
 };
 
-int slot_create(Slot& sl, long long n_cap, long long nnz_cap, int m) {
-  if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
-    return set_err(nullptr, IGS_EDEVICE, "cannot create a stream");
+int slot_create(Slot& sl, long long n_cap, long long nnz_cap, int m, hipStream_t shared = nullptr,
+                bool fp32 = false) {
+  if (shared) {
+    sl.stream = shared;
+  } else {
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
+      return set_err(nullptr, IGS_EDEVICE, "cannot create a stream");
+    sl.own_stream = true;
+  }
   igs_ctx* c = nullptr;
   igs_ctx* out = nullptr;
   int rc = common_create(&out, sl.stream, &c);
@@ -824,7 +832,16 @@ int slot_create(Slot& sl, long long n_cap, long long nnz_cap, int m) {
   c->op.row_ptr = c->d_row_ptr;
   c->op.col_idx = c->d_col;
   c->op.vals = c->d_vals;
-  rc = ensure_workspace(c, (int)std::min<long long>(m, std::min<long long>(n_cap, IGS_MAX_RESTART)));
+  const int mw = (int)std::min<long long>(m, std::min<long long>(n_cap, IGS_MAX_RESTART));
+  rc = ensure_workspace(c, mw);
+  if (rc == IGS_OK && fp32) {
+    // the FP32 copy of the values is sized for the capacity; each binding
+    // rounds the new operator into it
+    if (hipMemsetAsync(c->d_vals, 0, sizeof(double) * std::max<long long>(nnz_cap, 1),
+                       c->stream) != hipSuccess)
+      return set_err(nullptr, IGS_EDEVICE, "cannot clear a serving slot");
+    rc = ensure_fp32(c, mw);
+  }
   if (rc != IGS_OK) return set_err(nullptr, rc, "%s", c->err.c_str());
   return IGS_OK;
 }
@@ -833,7 +850,7 @@ void slot_destroy(Slot& sl) {
   if (sl.b) (void)hipFree(sl.b);
   if (sl.x) (void)hipFree(sl.x);
   if (sl.ctx) igs_destroy(sl.ctx);
-  if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  if (sl.stream && sl.own_stream) (void)hipStreamDestroy(sl.stream);
   sl = Slot{};
 }
 
@@ -987,5 +1004,522 @@ extern "C" int igs_serve(igs_request* reqs, int nreq, int slots, int64_t mem_cap
   for (Slot& x : sl) slot_destroy(x);
   for (int i = 0; i < nreq; ++i)
     if (reqs[i].rc == IGS_EDEVICE) return IGS_EDEVICE;
+  return IGS_OK;
+}
+
+// ===========================================================================
+// Batches: many independent solves advanced by each launch
+// ===========================================================================
+
+namespace {
+
+// One solve of a batch and where its restart loop stands (the same state
+// machine as igs_solve_opts, advanced one cycle at a time).
+struct Member {
+  igs_ctx* c = nullptr;
+  const double* b = nullptr;   // device
+  double* x = nullptr;         // device
+  int m = 0;                   // restart length min(restart, n)
+  long long maxit = 0;
+  long long its = 0;
+  int cycles = 0;
+  bool fresh = true;           // ||b|| not taken yet
+  bool final_check = false;
+  bool done = false;
+  bool converged = false;
+  int rc = IGS_ENOCONV;
+  int status = igs::kRunning;
+  double bnorm = 0.0, relres = NAN, arn = NAN;
+  int breakdowns = 0, fallbacks = 0, J_first = -1;
+};
+
+struct Batch {
+  hipStream_t stream = nullptr;
+  igs::Inst* d_tab = nullptr;
+  igs::Inst* h_tab = nullptr;   // pinned
+  Ctl* d_ctl = nullptr;
+  Ctl* h_ctl = nullptr;         // pinned
+  Member mem[igs::kMaxBatch];
+  std::string err;
+};
+
+struct BatchParams {
+  int gs = 2;
+  double tol = 0.0, tau = 1e-4, cycle_rtol = 0.0;
+  int final_v = 0, fp32 = 0, max_cycles = 0;
+};
+
+void batch_free(Batch& B) {
+  if (B.d_tab) (void)hipFree(B.d_tab);
+  if (B.d_ctl) (void)hipFree(B.d_ctl);
+  if (B.h_tab) (void)hipHostFree(B.h_tab);
+  if (B.h_ctl) (void)hipHostFree(B.h_ctl);
+  B.d_tab = nullptr;
+  B.d_ctl = nullptr;
+  B.h_tab = nullptr;
+  B.h_ctl = nullptr;
+}
+
+int batch_alloc(Batch& B, hipStream_t s) {
+  B.stream = s;
+  if (dalloc(&B.d_tab, igs::kMaxBatch) != hipSuccess || dalloc(&B.d_ctl, igs::kMaxBatch) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&B.h_tab), sizeof(igs::Inst) * igs::kMaxBatch,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&B.h_ctl), sizeof(Ctl) * igs::kMaxBatch,
+                    hipHostMallocDefault) != hipSuccess) {
+    batch_free(B);
+    return IGS_ENOMEM;
+  }
+  memset(B.h_tab, 0, sizeof(igs::Inst) * igs::kMaxBatch);
+  return IGS_OK;
+}
+
+// Put member k (context with workspace for its m, device b and x holding x0)
+// into the batch.
+void batch_add(Batch& B, int k, igs_ctx* c, const double* b, double* x, int restart,
+               long long maxit_opt) {
+  Member& M = B.mem[k];
+  M = Member{};
+  M.c = c;
+  M.b = b;
+  M.x = x;
+  M.m = (int)std::min<long long>(std::min<long long>(restart, c->n), IGS_MAX_RESTART);
+  M.maxit = maxit_opt > 0 ? maxit_opt : 20 * c->n;
+}
+
+#define BATCH_HIP(call)                                                                        \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      B.err = std::string(#call) + ": " + hipGetErrorString(e_);                               \
+      return IGS_EDEVICE;                                                                      \
+    }                                                                                          \
+  } while (0)
+
+// Fill row k of the host table from member k for the next cycle.
+void batch_row(Batch& B, int k, const BatchParams& p) {
+  const Member& M = B.mem[k];
+  igs::Inst& I = B.h_tab[k];
+  I.w = M.c->w;
+  I.w.fp32 = p.fp32;
+  I.op = M.c->op;
+  I.n = M.c->n;
+  I.b = M.b;
+  I.x = M.x;
+  I.its_before = M.its;
+  I.maxit = M.final_check ? M.its : M.maxit;   // a check cycle runs iteration 0 only
+  I.tol = p.tol;
+  I.tau = p.tau;
+  I.cycle_rtol = p.cycle_rtol;
+  I.m = M.m;
+  I.gs = p.gs;
+  I.final_v = p.final_v;
+  I.run_lsq = M.final_check ? 0 : 1;
+}
+
+// ||b|| and the finiteness of b and x0 for the members that just joined;
+// a member with non-finite input leaves with IGS_EINVAL and x untouched.
+int batch_admit(Batch& B, const BatchParams& p) {
+  igs::BatchRun r{};
+  r.d_tab = B.d_tab;
+  r.h_tab = B.h_tab;
+  r.stream = B.stream;
+  for (int k = 0; k < igs::kMaxBatch; ++k) {
+    Member& M = B.mem[k];
+    if (!M.c || M.done || !M.fresh) continue;
+    batch_row(B, k, p);
+    r.act[r.count++] = k;
+  }
+  if (r.count == 0) return IGS_OK;
+  BATCH_HIP(hipMemcpyAsync(B.d_tab, B.h_tab, sizeof(igs::Inst) * igs::kMaxBatch,
+                           hipMemcpyHostToDevice, B.stream));
+  BATCH_HIP(igs::batch_bnorm(r));
+  BATCH_HIP(igs::batch_ctl_gather(r, B.d_ctl));
+  BATCH_HIP(hipMemcpyAsync(B.h_ctl, B.d_ctl, sizeof(Ctl) * igs::kMaxBatch, hipMemcpyDeviceToHost,
+                           B.stream));
+  BATCH_HIP(hipStreamSynchronize(B.stream));
+  for (int q = 0; q < r.count; ++q) {
+    Member& M = B.mem[r.act[q]];
+    const Ctl& h = B.h_ctl[r.act[q]];
+    M.fresh = false;
+    M.bnorm = h.bnorm;
+    if (h.nonfinite_in > 0) {
+      M.rc = IGS_EINVAL;
+      M.done = true;
+    }
+  }
+  return IGS_OK;
+}
+
+// One restart cycle of every member still running: the steps of
+// igs_solve_opts, each launched once for all of them.
+int batch_cycle(Batch& B, const BatchParams& p) {
+  int rc = batch_admit(B, p);
+  if (rc != IGS_OK) return rc;
+  igs::BatchRun all{};
+  all.d_tab = B.d_tab;
+  all.h_tab = B.h_tab;
+  all.stream = B.stream;
+  int jmax = 0;
+  for (int k = 0; k < igs::kMaxBatch; ++k) {
+    Member& M = B.mem[k];
+    if (!M.c || M.done) continue;
+    batch_row(B, k, p);
+    all.act[all.count++] = k;
+    if (!M.final_check) jmax = std::max(jmax, M.m);
+  }
+  if (all.count == 0) return IGS_OK;
+  BATCH_HIP(hipMemcpyAsync(B.d_tab, B.h_tab, sizeof(igs::Inst) * igs::kMaxBatch,
+                           hipMemcpyHostToDevice, B.stream));
+  BATCH_HIP(igs::batch_residual(all));
+  // Iteration j runs for every member with j <= m (its tail step at j = m:
+  // no operator apply, the reduction without z); the kernels of a member
+  // whose cycle ended earlier return at once, as in a lone solve.
+  int ng_full[igs::kMaxBatch];
+  for (int j = 0; j <= jmax; ++j) {
+    igs::BatchRun sp = all, rz = all, rt = all, up = all;
+    sp.count = rz.count = rt.count = up.count = 0;
+    for (int q = 0; q < all.count; ++q) {
+      const int k = all.act[q];
+      const Member& M = B.mem[k];
+      const int mk = M.final_check ? 0 : M.m;   // a check cycle stops after iteration 0
+      if (j > mk) continue;
+      up.act[up.count++] = k;
+      if (j < M.m) {
+        sp.act[sp.count++] = k;
+        rz.act[rz.count++] = k;
+      } else {
+        rt.act[rt.count++] = k;
+      }
+    }
+    if (up.count == 0) continue;
+    BATCH_HIP(igs::batch_spmv(sp, j));
+    int ngz[igs::kMaxBatch], ngt[igs::kMaxBatch];
+    BATCH_HIP(igs::batch_reduce(rz, j, true, ngz));
+    BATCH_HIP(igs::batch_reduce(rt, j, false, ngt));
+    for (int q = 0; q < rz.count; ++q) ng_full[rz.act[q]] = ngz[q];
+    for (int q = 0; q < rt.count; ++q) ng_full[rt.act[q]] = ngt[q];
+    int ng[igs::kMaxBatch];
+    for (int q = 0; q < up.count; ++q) ng[q] = ng_full[up.act[q]];
+    BATCH_HIP(igs::batch_update(up, j, ng));
+  }
+  int mmax = 1;
+  for (int q = 0; q < all.count; ++q) mmax = std::max(mmax, B.mem[all.act[q]].m);
+  BATCH_HIP(igs::batch_lsq(all, mmax));
+  BATCH_HIP(igs::batch_xupdate(all));
+  BATCH_HIP(igs::batch_ctl_gather(all, B.d_ctl));
+  BATCH_HIP(hipMemcpyAsync(B.h_ctl, B.d_ctl, sizeof(Ctl) * igs::kMaxBatch, hipMemcpyDeviceToHost,
+                           B.stream));
+  BATCH_HIP(hipStreamSynchronize(B.stream));
+  for (int q = 0; q < all.count; ++q) {
+    Member& M = B.mem[all.act[q]];
+    const Ctl& h = B.h_ctl[all.act[q]];
+    const int J = h.J;
+    M.status = h.status;
+    M.breakdowns = h.breakdowns;
+    M.fallbacks = h.fallbacks;
+    if (M.cycles == 0 && !M.final_check) M.J_first = J;
+    M.cycles += 1;
+    M.relres = M.bnorm > 0 ? h.rho / M.bnorm : h.rho;
+    if (M.status == igs::kConvStart) {
+      M.converged = true;
+      M.rc = IGS_OK;
+      M.done = true;
+    } else if (M.status == igs::kNonfinite) {
+      M.rc = IGS_ENUMERIC;
+      M.its += J;
+      M.done = true;
+    } else if (M.final_check) {
+      M.rc = IGS_ENOCONV;
+      M.done = true;
+    } else {
+      M.its += J;
+      M.arn = M.bnorm > 0 ? h.gabs / M.bnorm : h.gabs;
+      if (J == 0) {
+        M.rc = IGS_ENUMERIC;
+        M.done = true;
+      } else if (M.its >= M.maxit || (p.max_cycles > 0 && M.cycles >= p.max_cycles)) {
+        M.final_check = true;
+      }
+    }
+  }
+  return IGS_OK;
+}
+
+#undef BATCH_HIP
+
+void member_info(const Member& M, igs_info* info, double seconds) {
+  if (!info) return;
+  info->iters = M.its;
+  info->cycles = M.cycles;
+  info->relres_true = M.relres;
+  info->arnoldi_relres = M.arn;
+  info->bnorm = M.bnorm;
+  info->converged = M.converged ? 1 : 0;
+  info->breakdowns = M.breakdowns;
+  info->lagnorm_fallbacks = M.fallbacks;
+  info->last_cycle_status = M.status;
+  info->first_cycle_J = M.J_first;
+  info->reserved = 0;
+  info->seconds = seconds;
+}
+
+// Options a batch runs with (the subset of igs_solve_opts it supports).
+int batch_params(const igs_opts& o, int gs_iters, double tol, BatchParams* p, std::string* why) {
+  if (o.two_reduce) {
+    *why = "the two-reduce comparator runs in igs_solve_opts only";
+    return IGS_ENOTIMPL;
+  }
+  if (o.keep_first_basis) {
+    *why = "keep_first_basis runs in igs_solve_opts only";
+    return IGS_ENOTIMPL;
+  }
+  p->gs = gs_iters;
+  p->tol = tol;
+  p->tau = o.lagnorm_tau > 0.0 ? o.lagnorm_tau : 1e-4;
+  p->final_v = o.final_basis_vector ? 1 : 0;
+  p->fp32 = o.inner_fp32 ? 1 : 0;
+  p->cycle_rtol = p->fp32 ? (o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5) : 0.0;
+  p->max_cycles = o.max_cycles;
+  return IGS_OK;
+}
+
+}  // namespace
+
+extern "C" int igs_solve_batch(igs_ctx* const* ctxs, const double* const* b, double* const* x,
+                               int count, int restart, double tol, int gs_iters,
+                               const igs_opts* opts, igs_info* infos, int* rcs) {
+  if (!ctxs || !b || !x || count < 1 || count > IGS_MAX_BATCH || !ctxs[0])
+    return set_err(nullptr, IGS_EINVAL, "invalid batch arguments (1 <= count <= %d)", IGS_MAX_BATCH);
+  igs_ctx* c0 = ctxs[0];
+  c0->err.clear();
+  if (restart < 1) return set_err(c0, IGS_EINVAL, "restart must be >= 1");
+  if (!(tol >= 0.0) || !isfinite(tol)) return set_err(c0, IGS_EINVAL, "tol must be finite, >= 0");
+  if (gs_iters != 1 && gs_iters != 2) return set_err(c0, IGS_EINVAL, "gs_iters must be 1 or 2");
+  igs_opts o{};
+  if (opts) o = *opts;
+  BatchParams p;
+  std::string why;
+  int rc = batch_params(o, gs_iters, tol, &p, &why);
+  if (rc != IGS_OK) return set_err(c0, rc, "%s", why.c_str());
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_OR_FAIL(c0, hipSetDevice(c0->device));
+  for (int k = 0; k < count; ++k) {
+    igs_ctx* c = ctxs[k];
+    if (!c || !b[k] || !x[k]) return set_err(c0, IGS_EINVAL, "member %d: NULL context or vector", k);
+    if (c->device != c0->device) return set_err(c0, IGS_EINVAL, "member %d is on another device", k);
+    if (c->op.dense) return set_err(c0, IGS_ENOTIMPL, "member %d: batches take CSR operators", k);
+    if ((reinterpret_cast<uintptr_t>(b[k]) | reinterpret_cast<uintptr_t>(x[k])) % 16 != 0)
+      return set_err(c0, IGS_EINVAL, "member %d: b and x must be 16-byte aligned", k);
+    for (int q = 0; q < k; ++q)
+      if (ctxs[q] == c) return set_err(c0, IGS_EINVAL, "member %d repeats a context", k);
+  }
+  for (int k = 0; k < count; ++k) {
+    igs_ctx* c = ctxs[k];
+    const int m = (int)std::min<long long>(std::min<long long>(restart, c->n), IGS_MAX_RESTART);
+    rc = ensure_workspace(c, m);
+    if (rc == IGS_OK && p.fp32) rc = ensure_fp32(c, m);
+    if (rc != IGS_OK) return set_err(c0, rc, "member %d: %s", k, c->err.c_str());
+    // work the caller queued on the member's own stream comes first
+    HIP_OR_FAIL(c0, hipStreamSynchronize(c->stream));
+  }
+  Batch B;
+  if (batch_alloc(B, c0->stream) != IGS_OK)
+    return set_err(c0, IGS_ENOMEM, "cannot allocate the batch tables");
+  for (int k = 0; k < count; ++k) batch_add(B, k, ctxs[k], b[k], x[k], restart, o.maxit);
+  while (rc == IGS_OK) {
+    bool running = false;
+    for (int k = 0; k < count; ++k) running |= !B.mem[k].done;
+    if (!running) break;
+    rc = batch_cycle(B, p);
+  }
+  batch_free(B);
+  if (rc != IGS_OK) return set_err(c0, rc, "%s", B.err.c_str());
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = IGS_OK;
+  for (int k = 0; k < count; ++k) {
+    member_info(B.mem[k], infos ? infos + k : nullptr, secs);
+    if (rcs) rcs[k] = B.mem[k].rc;
+    if (B.mem[k].rc < 0 && worst >= 0) worst = B.mem[k].rc;
+    if (B.mem[k].rc == IGS_ENOCONV && worst == IGS_OK) worst = IGS_ENOCONV;
+  }
+  if (worst < 0) set_err(c0, worst, "a member of the batch failed (see its return code)");
+  else if (worst == IGS_ENOCONV) set_err(c0, worst, "a member of the batch did not converge");
+  return worst;
+}
+
+extern "C" int igs_serve_batched(igs_request* reqs, int nreq, int batch, int64_t mem_cap,
+                                 int restart, double tol, int gs_iters, const igs_opts* opts,
+                                 double* wall_seconds) {
+  if (!reqs || nreq < 0 || batch < 1 || batch > IGS_MAX_BATCH || mem_cap <= 0 || restart < 1)
+    return set_err(nullptr, IGS_EINVAL, "invalid serving arguments (1 <= batch <= %d)",
+                   IGS_MAX_BATCH);
+  if (!(tol >= 0.0) || !isfinite(tol) || (gs_iters != 1 && gs_iters != 2))
+    return set_err(nullptr, IGS_EINVAL, "invalid tol or gs_iters");
+  if (nreq == 0) return IGS_OK;
+  igs_opts o{};
+  if (opts) o = *opts;
+  o.keep_first_basis = 0;
+  o.profile = 0;
+  BatchParams p;
+  std::string why;
+  int rc = batch_params(o, gs_iters, tol, &p, &why);
+  if (rc != IGS_OK) return set_err(nullptr, rc, "%s", why.c_str());
+  long long n_cap = 1, nnz_cap = 0;
+  std::vector<long long> need(nreq);
+  for (int i = 0; i < nreq; ++i) {
+    reqs[i].rc = IGS_EINVAL;
+    reqs[i].iters = 0;
+    reqs[i].status = 0;
+    reqs[i].t_admit = reqs[i].t_done = -1.0;
+    if (reqs[i].n < 1 || reqs[i].nnz < 0 || !reqs[i].b || !reqs[i].x)
+      return set_err(nullptr, IGS_EINVAL, "request %d: invalid size or NULL array", i);
+    n_cap = std::max<long long>(n_cap, reqs[i].n);
+    nnz_cap = std::max<long long>(nnz_cap, reqs[i].nnz);
+    need[i] = request_bytes(reqs[i].n, reqs[i].nnz, restart, p.fp32 != 0);
+    if (need[i] > mem_cap)
+      return set_err(nullptr, IGS_EINVAL, "request %d needs %lld bytes, more than the cap", i,
+                     need[i]);
+  }
+  hipStream_t stream = nullptr;
+  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
+    return set_err(nullptr, IGS_EDEVICE, "cannot create a stream");
+  std::vector<Slot> sl(batch);
+  Batch B;
+  rc = batch_alloc(B, stream) == IGS_OK ? IGS_OK : set_err(nullptr, IGS_ENOMEM, "batch tables");
+  for (int k = 0; k < batch && rc == IGS_OK; ++k)
+    rc = slot_create(sl[k], n_cap, nnz_cap, restart, stream, p.fp32 != 0);
+  auto cleanup = [&]() {
+    for (Slot& x : sl) slot_destroy(x);
+    batch_free(B);
+    (void)hipStreamDestroy(stream);
+  };
+  if (rc != IGS_OK) {
+    cleanup();
+    return rc;
+  }
+  std::vector<int> order(nreq);
+  for (int i = 0; i < nreq; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return reqs[a].arrival < reqs[b].arrival; });
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<int> queue;
+  bool closed = false;
+  bool stop = false;   // the loop ended early: arrivals stop too
+  const auto t0 = std::chrono::steady_clock::now();
+  auto since = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  // arrivals: each request joins the queue at its arrival time
+  std::thread arrivals([&]() {
+    for (int idx = 0; idx < nreq; ++idx) {
+      const int i = order[idx];
+      const double at = reqs[i].arrival;
+      const auto when = t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                 std::chrono::duration<double>(at > 0 ? at : 0.0));
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait_until(lk, when, [&] { return stop; });
+        if (stop) break;
+        queue.push_back(i);
+      }
+      cv.notify_all();
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      closed = true;
+    }
+    cv.notify_all();
+  });
+  std::vector<int> req_of(batch, -1);
+  long long reserved = 0;
+  int fatal = IGS_OK;
+  while (fatal == IGS_OK) {
+    // admit: the oldest arrived requests, while a member is free and the
+    // memory they hold fits the cap
+    std::vector<int> admitted;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      bool any = false;
+      for (int k = 0; k < batch; ++k) any |= (req_of[k] >= 0);
+      if (!any)
+        cv.wait(lk, [&] { return !queue.empty() || closed; });
+      for (int k = 0; k < batch && !queue.empty(); ++k) {
+        if (req_of[k] >= 0) continue;
+        const int i = queue.front();
+        if (reserved + need[i] > mem_cap) break;
+        queue.pop_front();
+        reserved += need[i];
+        req_of[k] = i;
+        admitted.push_back(k);
+      }
+      if (!any && admitted.empty() && closed && queue.empty()) break;
+    }
+    for (int k : admitted) {
+      igs_request& r = reqs[req_of[k]];
+      r.t_admit = since();
+      igs_ctx* c = sl[k].ctx;
+      int brc = slot_bind(c, r.n, r.nnz, r.row_ptr, r.col_idx, r.vals);
+      if (brc == IGS_OK &&
+          (hipMemcpyAsync(sl[k].b, r.b, sizeof(double) * r.n, hipMemcpyHostToDevice, stream) !=
+               hipSuccess ||
+           hipMemsetAsync(sl[k].x, 0, sizeof(double) * r.n, stream) != hipSuccess))
+        brc = IGS_EDEVICE;
+      if (brc != IGS_OK) {
+        r.rc = brc;
+        r.t_done = since();
+        reserved -= need[req_of[k]];
+        req_of[k] = -1;
+        B.mem[k] = Member{};
+        if (brc == IGS_EDEVICE) fatal = brc;
+        continue;
+      }
+      batch_add(B, k, c, sl[k].b, sl[k].x, restart, o.maxit);
+    }
+    if (fatal != IGS_OK) break;
+    bool running = false;
+    for (int k = 0; k < batch; ++k) running |= (req_of[k] >= 0);
+    if (!running) continue;
+    rc = batch_cycle(B, p);
+    if (rc != IGS_OK) {
+      fatal = rc;
+      break;
+    }
+    // completions: copy x back, free the member and its memory
+    bool copied = false;
+    for (int k = 0; k < batch; ++k) {
+      if (req_of[k] < 0 || !B.mem[k].done) continue;
+      igs_request& r = reqs[req_of[k]];
+      if (B.mem[k].rc == IGS_OK || B.mem[k].rc == IGS_ENOCONV || B.mem[k].rc == IGS_ENUMERIC) {
+        if (hipMemcpyAsync(r.x, sl[k].x, sizeof(double) * r.n, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess)
+          fatal = IGS_EDEVICE;
+        copied = true;
+      }
+    }
+    if (copied && hipStreamSynchronize(stream) != hipSuccess) fatal = IGS_EDEVICE;
+    for (int k = 0; k < batch; ++k) {
+      if (req_of[k] < 0 || !B.mem[k].done) continue;
+      igs_request& r = reqs[req_of[k]];
+      r.rc = B.mem[k].rc;
+      r.iters = B.mem[k].its;
+      r.status = B.mem[k].status;
+      r.t_done = since();
+      reserved -= need[req_of[k]];
+      req_of[k] = -1;
+      B.mem[k] = Member{};
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stop = true;
+  }
+  cv.notify_all();
+  arrivals.join();
+  if (wall_seconds) *wall_seconds = since();
+  const std::string why_fatal = B.err;
+  cleanup();
+  if (fatal != IGS_OK) return set_err(nullptr, fatal, "serving stopped: %s", why_fatal.c_str());
   return IGS_OK;
 }

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libigs.so")
 
 IGS_OK, IGS_ENOCONV, IGS_EINVAL, IGS_ENOMEM, IGS_EDEVICE, IGS_ENOTIMPL, IGS_ENUMERIC = 0, 1, -1, -2, -3, -4, -5
 IGS_MAX_RESTART = 512
+IGS_MAX_BATCH = 32
 (IGS_K_SPMV, IGS_K_REDUCE, IGS_K_UPDATE, IGS_K_XUPDATE, IGS_K_RESIDUAL, IGS_K_COUNT) = range(6)
 KERNEL_NAMES = ("spmv", "reduce", "update", "xupdate", "residual")
 CYCLE_STATUS = ("running", "converged_at_start", "arnoldi_converged", "full", "breakdown",
@@ -25,7 +26,7 @@ EXPORTED = (
     "igs_create", "igs_create_dense", "igs_solve", "igs_solve_opts", "igs_destroy",
     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
     "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
-    "igs_serve",
+    "igs_serve", "igs_solve_batch", "igs_serve_batched",
 )
 
 
@@ -92,6 +93,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "igs_profile_reset": (c_int, [P]),
         "igs_serve": (c_int, [POINTER(IgsRequest), c_int, c_int, c_int64, c_int, c_double, c_int,
                               POINTER(IgsOpts), POINTER(c_double)]),
+        "igs_solve_batch": (c_int, [POINTER(P), POINTER(P), POINTER(P), c_int, c_int, c_double,
+                                    c_int, POINTER(IgsOpts), POINTER(IgsInfo), POINTER(c_int)]),
+        "igs_serve_batched": (c_int, [POINTER(IgsRequest), c_int, c_int, c_int64, c_int, c_double,
+                                      c_int, POINTER(IgsOpts), POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -214,4 +219,32 @@ def igs_serve(reqs, slots, mem_cap, restart, tol, gs_iters, opts: IgsOpts | None
                                   float(tol), int(gs_iters), ctypes.byref(opts) if opts else None,
                                   ctypes.byref(wall))
     _check("igs_serve", rc, None)
+    return rc, wall.value
+
+
+def igs_solve_batch(ctxs, bs, xs, restart, tol, gs_iters, opts: IgsOpts | None = None):
+    """ctxs: contexts; bs, xs: device vectors (tensors or addresses), one per
+    context.  Returns (return code, [info dict], [member return code]);
+    raises when the call itself is invalid (then no member ran)."""
+    k = len(ctxs)
+    arr = lambda vals: (c_void_p * k)(*[_ptr(v).value for v in vals])
+    infos = (IgsInfo * k)()
+    unset = 99
+    rcs = (c_int * k)(*([unset] * k))
+    ctx_arr = (c_void_p * k)(*[c.value if isinstance(c, c_void_p) else int(c) for c in ctxs])
+    rc = load_library().igs_solve_batch(ctx_arr, arr(bs), arr(xs), k, int(restart), float(tol),
+                                        int(gs_iters), ctypes.byref(opts) if opts else None,
+                                        infos, rcs)
+    if all(r == unset for r in rcs):   # the call itself failed: no member ran
+        _check("igs_solve_batch", rc, ctxs[0] if k else None, allow=(IGS_OK, IGS_ENOCONV))
+    return rc, [i.as_dict() for i in infos], list(rcs)
+
+
+def igs_serve_batched(reqs, batch, mem_cap, restart, tol, gs_iters, opts: IgsOpts | None = None):
+    """As igs_serve, with up to `batch` requests advanced by each launch."""
+    wall = c_double(0.0)
+    rc = load_library().igs_serve_batched(reqs, len(reqs), int(batch), int(mem_cap), int(restart),
+                                          float(tol), int(gs_iters),
+                                          ctypes.byref(opts) if opts else None, ctypes.byref(wall))
+    _check("igs_serve_batched", rc, None)
     return rc, wall.value

@@ -10,10 +10,14 @@ import numpy as np
 from . import igs as _igs
 
 
-def serve(systems, slots=8, mem_cap=64 << 30, restart=50, tol=1e-12, gs_iters=2, **opts):
+def serve(systems, slots=8, mem_cap=64 << 30, restart=50, tol=1e-12, gs_iters=2, batch=0,
+          **opts):
     """systems: iterable of (csr, b, arrival_seconds), csr with row_ptr,
-    col_idx, vals.  Returns (results, wall_seconds, rc) where results[i] is a
-    dict with x (numpy), iters, rc, status, t_admit, t_done, arrival."""
+    col_idx, vals.  batch = 0: `slots` solver slots on streams of their own
+    (igs_serve); batch > 0: up to `batch` requests advanced by each launch on
+    one stream (igs_serve_batched).  Returns (results, wall_seconds, rc)
+    where results[i] is a dict with x (numpy), iters, rc, status, t_admit,
+    t_done, arrival."""
     systems = list(systems)
     keep = []
     reqs = (_igs.IgsRequest * len(systems))()
@@ -32,7 +36,10 @@ def serve(systems, slots=8, mem_cap=64 << 30, restart=50, tol=1e-12, gs_iters=2,
     o = _igs.IgsOpts()
     for k, v in opts.items():
         setattr(o, k, v)
-    rc, wall = _igs.igs_serve(reqs, slots, mem_cap, restart, tol, gs_iters, o)
+    if batch > 0:
+        rc, wall = _igs.igs_serve_batched(reqs, batch, mem_cap, restart, tol, gs_iters, o)
+    else:
+        rc, wall = _igs.igs_serve(reqs, slots, mem_cap, restart, tol, gs_iters, o)
     out = []
     for i, r in enumerate(reqs):
         out.append({"x": keep[i][4], "iters": int(r.iters), "rc": int(r.rc), "status": int(r.status),

@@ -85,3 +85,19 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(solvers, bs, x0s=None, restart=50, tol=1e-12, gs_iters=2, **opts):
+    """Solve one system per Solver together (igs_solve_batch).  Returns
+    (xs, rc, infos, rcs); xs are device tensors."""
+    torch = _torch()
+    bds = [s.to_device(b) for s, b in zip(solvers, bs)]
+    xs = [s.to_device(x).clone() if x0s is not None and x is not None else torch.zeros_like(bd)
+          for s, bd, x in zip(solvers, bds, x0s if x0s is not None else [None] * len(bds))]
+    o = _igs.IgsOpts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    torch.cuda.synchronize()
+    rc, infos, rcs = _igs.igs_solve_batch([s.ctx for s in solvers], bds, xs, restart, tol,
+                                          gs_iters, o)
+    return xs, rc, infos, rcs

@@ -123,3 +123,20 @@ def test_serve_rejects_bad_arguments_without_gpu_work(lib):
     assert r.rc == igs.IGS_EINVAL and r.t_admit == -1.0
     with pytest.raises(igs.IgsError):
         igs.igs_serve(reqs, 0, 1 << 30, 10, 1e-10, 2)
+
+
+def test_batch_entry_points_reject_bad_arguments_without_gpu_work(lib):
+    import numpy as np
+    from paper_2205_07805_amd import igs
+    L = igs.load_library()
+    assert L.igs_solve_batch(None, None, None, 0, 10, 1e-10, 2, None, None, None) == igs.IGS_EINVAL
+    reqs = (igs.IgsRequest * 1)()
+    b = np.ones(4)
+    x = np.zeros(4)
+    reqs[0].n, reqs[0].nnz, reqs[0].b, reqs[0].x = 4, 4, b.ctypes.data, x.ctypes.data
+    for batch in (0, igs.IGS_MAX_BATCH + 1):
+        assert L.igs_serve_batched(reqs, 1, batch, 1 << 30, 10, 1e-10, 2, None, None) == igs.IGS_EINVAL
+    o = igs.IgsOpts(two_reduce=1)
+    assert L.igs_serve_batched(reqs, 1, 4, 1 << 30, 10, 1e-10, 2, ctypes.byref(o), None) == \
+        igs.IGS_ENOTIMPL
+    assert L.igs_serve_batched(reqs, 1, 4, 1024, 10, 1e-10, 2, None, None) == igs.IGS_EINVAL
