@@ -100,6 +100,15 @@ typedef struct igs_opts {
   double inner_rtol;    /* inner_fp32: a cycle also ends once its Arnoldi
                            residual is <= inner_rtol * ||r0|| of the cycle;
                            <= 0 means 1e-5                                     */
+  int batch_reduce_rows;  /* batches (igs_solve_batch, igs_serve_batched): at
+                             least this many rows per block of the fused
+                             reduction (fewer, larger blocks when many
+                             instances share a launch).  1: the grid a lone
+                             solve launches (then every member is
+                             bit-identical to igs_solve_opts); <= 0: 4096    */
+  int batch_update_tiles; /* batches: at least this many 4-row-per-thread
+                             tiles per block of the update.  1: the lone
+                             grid; <= 0: 4                                   */
 } igs_opts;
 
 /* Result summary of a solve.  Any pointer argument of this type may be NULL. */

@@ -170,6 +170,8 @@ struct BatchRun {
   int act[kMaxBatch];  // table rows taking part
   int count;
   hipStream_t stream;
+  int reduce_rows;     // least rows per block of the fused reduction (1: lone grid)
+  int update_tiles;    // least tiles per block of the update (1: lone grid)
 };
 
 // ||b|| and the finiteness check of the instances act[0..count).

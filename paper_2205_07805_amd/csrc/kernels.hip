@@ -2162,9 +2162,14 @@ static hipError_t batch_reduce_t(const BatchRun& r, int j, bool with_z, int* ngr
   }
   int nb[kMaxBatch];
   long long rpb[kMaxBatch];
+  const long long rmin = r.reduce_rows > 1 ? r.reduce_rows : 1;
   for (int k = 0; k < r.count; ++k) {
     ReduceShape sh = sh0;
-    reduce_rows(sh, r.h_tab[r.act[k]].n, cap);
+    // an instance's grid depends on its own n and j only, never on the
+    // other members of the launch
+    const long long n = r.h_tab[r.act[k]].n;
+    const long long want = (n + rmin - 1) / rmin;
+    reduce_rows(sh, n, (int)(want < cap ? want : cap));
     nb[k] = sh.nblocks;
     rpb[k] = sh.rows_per_block;
     ngroups[k] = reduce_groups(sh.nblocks);
@@ -2194,8 +2199,13 @@ static hipError_t batch_update_t(const BatchRun& r, int j, const int* ngroups) {
   const size_t lds = update_lds_doubles(j) * sizeof(double);
   int nb[kMaxBatch];
   long long ng[kMaxBatch];
+  const long long tmin = r.update_tiles > 1 ? r.update_tiles : 1;
   for (int k = 0; k < r.count; ++k) {
-    nb[k] = (int)update_grid(lone, r.h_tab[r.act[k]].n, update_tile_rows<T>(), lds);
+    const long long n = r.h_tab[r.act[k]].n;
+    const long long g = update_grid(lone, n, update_tile_rows<T>(), lds);
+    const long long tiles = (n + update_tile_rows<T>() - 1) / update_tile_rows<T>();
+    const long long want = (tiles + tmin - 1) / tmin;
+    nb[k] = (int)(want < g ? want : g);
     ng[k] = ngroups[k];
   }
   BatchMap m;

@@ -1047,6 +1047,7 @@ struct BatchParams {
   int gs = 2;
   double tol = 0.0, tau = 1e-4, cycle_rtol = 0.0;
   int final_v = 0, fp32 = 0, max_cycles = 0;
+  int reduce_rows = 4096, update_tiles = 4;
 };
 
 void batch_free(Batch& B) {
@@ -1124,6 +1125,8 @@ int batch_admit(Batch& B, const BatchParams& p) {
   r.d_tab = B.d_tab;
   r.h_tab = B.h_tab;
   r.stream = B.stream;
+  r.reduce_rows = p.reduce_rows;
+  r.update_tiles = p.update_tiles;
   for (int k = 0; k < igs::kMaxBatch; ++k) {
     Member& M = B.mem[k];
     if (!M.c || M.done || !M.fresh) continue;
@@ -1160,6 +1163,8 @@ int batch_cycle(Batch& B, const BatchParams& p) {
   all.d_tab = B.d_tab;
   all.h_tab = B.h_tab;
   all.stream = B.stream;
+  all.reduce_rows = p.reduce_rows;
+  all.update_tiles = p.update_tiles;
   int jmax = 0;
   for (int k = 0; k < igs::kMaxBatch; ++k) {
     Member& M = B.mem[k];
@@ -1281,6 +1286,8 @@ int batch_params(const igs_opts& o, int gs_iters, double tol, BatchParams* p, st
   p->fp32 = o.inner_fp32 ? 1 : 0;
   p->cycle_rtol = p->fp32 ? (o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5) : 0.0;
   p->max_cycles = o.max_cycles;
+  p->reduce_rows = o.batch_reduce_rows > 0 ? o.batch_reduce_rows : 4096;
+  p->update_tiles = o.batch_update_tiles > 0 ? o.batch_update_tiles : 4;
   return IGS_OK;
 }
 

@@ -35,7 +35,8 @@ class IgsOpts(ctypes.Structure):
                 ("profile", c_int), ("max_cycles", c_int), ("keep_first_basis", c_int),
                 ("profile_kernels", c_int), ("inner_fp32", c_int), ("two_reduce", c_int),
                 ("reserved", c_int * 1),
-                ("inner_rtol", c_double)]
+                ("inner_rtol", c_double), ("batch_reduce_rows", c_int),
+                ("batch_update_tiles", c_int)]
 
 
 class IgsInfo(ctypes.Structure):

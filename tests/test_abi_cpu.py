@@ -58,6 +58,7 @@ int main(void) {
          offsetof(igs_opts, keep_first_basis), sizeof(igs_info), offsetof(igs_info, seconds));
   printf("%d %d\n", IGS_MAX_RESTART, IGS_K_COUNT);
   printf("%zu %zu\n", offsetof(igs_opts, inner_fp32), offsetof(igs_opts, inner_rtol));
+  printf("%zu\n", offsetof(igs_opts, batch_update_tiles));
   printf("%zu %zu %zu %zu %zu\n", sizeof(igs_request), offsetof(igs_request, arrival),
          offsetof(igs_request, iters), offsetof(igs_request, rc), offsetof(igs_request, status));
   return 0;
@@ -76,10 +77,11 @@ int main(void) {
     from paper_2205_07805_amd import igs
     assert vals[5] == igs.IGS_MAX_RESTART and vals[6] == igs.IGS_K_COUNT
     assert vals[7] == IgsOpts.inner_fp32.offset and vals[8] == IgsOpts.inner_rtol.offset
+    assert vals[9] == IgsOpts.batch_update_tiles.offset
     from paper_2205_07805_amd.igs import IgsRequest
-    assert vals[9] == ctypes.sizeof(IgsRequest) and vals[10] == IgsRequest.arrival.offset
-    assert vals[11] == IgsRequest.iters.offset and vals[12] == IgsRequest.rc.offset
-    assert vals[13] == IgsRequest.status.offset
+    assert vals[10] == ctypes.sizeof(IgsRequest) and vals[11] == IgsRequest.arrival.offset
+    assert vals[12] == IgsRequest.iters.offset and vals[13] == IgsRequest.rc.offset
+    assert vals[14] == IgsRequest.status.offset
 
 
 def test_missing_library_fails_loudly(tmp_path):

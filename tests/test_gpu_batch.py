@@ -2,10 +2,18 @@
 by each launch) and igs_serve_batched (continuous batching at restart-cycle
 granularity on one stream).
 
-Bar: every member's x is bit-identical to a lone igs_solve_opts of the same
-system with the same arguments, with the same iteration count and return
-code; the relative residual of each converged member meets the tolerance
-against the oracle's operator.
+Bars:
+* with the lone-solve grids (batch_reduce_rows = batch_update_tiles = 1)
+  every member's x is bit-identical to a lone igs_solve_opts of the same
+  system, with the same iteration count and return code;
+* with the default coarse grids (fewer, larger blocks per instance) each
+  member's x is bit-identical alone (a batch of one) and in the mix, since
+  an instance's grid depends on its own size only; against igs_solve_opts
+  it differs by summation order only: the same tolerance is met, the
+  iteration count agrees within 2 (FP32 cycles: within 10 + 5%) and x within
+  1e3 tol (relative);
+* the relative residual of each converged member meets the tolerance
+  against the oracle's operator.
 """
 import numpy as np
 import pytest
@@ -49,6 +57,7 @@ def batch(systems, restart, tol, gs, **opts):
 
 
 SIDES = [(20, 5.0), (33, 40.0), (47, 1.0), (64, 80.0), (90, 20.0), (128, 50.0)]
+LONE_GRIDS = dict(batch_reduce_rows=1, batch_update_tiles=1)
 
 
 @pytest.mark.parametrize("gs,fp32", [(2, 0), (1, 0), (2, 1)])
@@ -56,7 +65,7 @@ def test_solve_batch_matches_lone(torch, gs, fp32):
     systems = [(W.convdiff2d(s, pe), W.rhs_normal(s * s, 10 + s)) for s, pe in SIDES]
     restart, tol = 30, 1e-12
     print(f"batch of {len(systems)} gs={gs} fp32={fp32}", flush=True)
-    xs, rc, infos, rcs = batch(systems, restart, tol, gs, inner_fp32=fp32)
+    xs, rc, infos, rcs = batch(systems, restart, tol, gs, inner_fp32=fp32, **LONE_GRIDS)
     assert rc == 0 and rcs == [0] * len(systems)
     for (a, b), x, info in zip(systems, xs, infos):
         x1, rc1, info1 = lone(a, b, restart, tol, gs, inner_fp32=fp32)
@@ -78,9 +87,10 @@ def test_solve_batch_mixed_outcomes(torch):
                (tiny, W.rhs_normal(tiny.n, 2)), (good, bad_b)]
     restart, tol = 30, 1e-12
     print("batch with mixed outcomes", flush=True)
-    xs, rc, infos, rcs = batch(systems, restart, tol, 2, maxit=0)
+    xs, rc, infos, rcs = batch(systems, restart, tol, 2, maxit=0, **LONE_GRIDS)
     # a small budget for the second call: the ordinary member stops early
-    xs2, rc2, infos2, rcs2 = batch(systems[:1] + systems[2:3], restart, tol, 2, maxit=45)
+    xs2, rc2, infos2, rcs2 = batch(systems[:1] + systems[2:3], restart, tol, 2, maxit=45,
+                                   **LONE_GRIDS)
     assert rcs[3] == -1 and np.all(xs[3] == 0.0)
     for k in range(3):
         x1, rc1, info1 = lone(*systems[k], restart, tol, 2)
@@ -115,7 +125,7 @@ def test_serve_batched_matches_lone(torch, fp32):
     restart, tol = 30, 1e-12
     print(f"serve_batched 24 requests fp32={fp32}", flush=True)
     res, wall, rc = serve([(q.a, q.b, q.arrival) for q in trace], batch=8, mem_cap=1 << 30,
-                          restart=restart, tol=tol, gs_iters=2, inner_fp32=fp32)
+                          restart=restart, tol=tol, gs_iters=2, inner_fp32=fp32, **LONE_GRIDS)
     assert rc == 0
     for q, r in zip(trace, res):
         x1, rc1, info1 = lone(q.a, q.b, restart, tol, 2, inner_fp32=fp32)
@@ -135,9 +145,36 @@ def test_serve_batched_memory_cap_and_bad_request(torch):
     bad.col_idx[3] = -1
     systems = [(a, W.rhs_normal(a.n, 60 + i), 0.0) for i in range(5)] + [(bad, W.rhs_normal(a.n, 9), 0.0)]
     print("serve_batched under a cap of 1.5 requests", flush=True)
-    res, _, rc = serve(systems, batch=8, mem_cap=int(1.5 * need), restart=30, tol=1e-10)
+    res, _, rc = serve(systems, batch=8, mem_cap=int(1.5 * need), restart=30, tol=1e-10,
+                       **LONE_GRIDS)
     assert rc == 0 and [r["rc"] for r in res] == [0] * 5 + [-1]
     spans = sorted((r["t_admit"], r["t_done"]) for r in res[:5])
     assert all(spans[k][0] >= spans[k - 1][1] for k in range(1, 5))
     x1, _, _ = lone(a, systems[2][1], 30, 1e-10, 2)
     assert np.array_equal(res[2]["x"], x1)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_solve_batch_coarse_grids_alone_equals_mix(torch, fp32):
+    """Default batch grids: alone (a batch of one) and in the mix agree bit
+    for bit; against igs_solve_opts they agree to the tolerance."""
+    systems = [(W.convdiff2d(s, pe), W.rhs_normal(s * s, 30 + s)) for s, pe in SIDES]
+    systems.append((W.convdiff2d(300, 30.0), W.rhs_normal(90000, 7)))   # many blocks per instance
+    restart, tol = 30, 1e-12
+    print(f"coarse-grid batch of {len(systems)} fp32={fp32}", flush=True)
+    xs, rc, infos, rcs = batch(systems, restart, tol, 2, inner_fp32=fp32)
+    assert rc == 0 and rcs == [0] * len(systems)
+    for (a, b), x, info in zip(systems, xs, infos):
+        xa, rca, infa, _ = batch([(a, b)], restart, tol, 2, inner_fp32=fp32)
+        assert rca == 0 and infa[0]["iters"] == info["iters"]
+        assert np.array_equal(xa[0], x), f"n={a.n}: alone and in the mix differ"
+        x1, rc1, info1 = lone(a, b, restart, tol, 2, inner_fp32=fp32)
+        rel = np.linalg.norm(b - O.as_operator(a).matvec(x)) / np.linalg.norm(b)
+        dx = np.abs(x - x1).max() / np.abs(x1).max()
+        print(f"  n={a.n:6d} iters {info['iters']:5d} (lone {info1['iters']}) relres {rel:.2e} "
+              f"max|x - x_lone|/max|x_lone| {dx:.1e}", flush=True)
+        # FP32 cycles round differently under another summation order, which
+        # can move a cycle's end by a few iterations
+        slack = 2 if not fp32 else 10 + info1["iters"] // 20
+        assert rel <= tol and abs(info["iters"] - info1["iters"]) <= slack
+        assert dx <= 1e3 * tol
