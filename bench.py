@@ -131,53 +131,58 @@ def mixed_precision_compare(torch, W, Solver, igs, dev, steps, grid=96, restart=
     return out
 
 
-def serving_compare(W, serve, count, slots, mem_cap=64 << 30, restart=50, tol=1e-12):
+def serving_compare(W, serve, count, slots, batch, mem_cap=64 << 30, restart=50, tol=1e-12):
     """The serving trace (2D convection-diffusion, sides uniform on [32, 512],
     Pe uniform on [1, 100], Poisson arrivals at 200/s, b seeded per request)
-    served three ways through igs_serve: the plain FP64 solver one request at
-    a time (a queue alone), continuous batching over `slots` streams in FP64,
-    and the same with FP32 cycles inside FP64 restarts.  Latency is completion
-    minus arrival; throughput is requests over the time to the last
-    completion.  Every result's relative residual is checked on the host with
-    scipy (relres <= tol implies backward error <= tol)."""
+    served four ways: the plain FP64 solver one request at a time (a queue
+    alone); continuous batching over `slots` solver streams (igs_serve); and
+    continuous batching with batched kernels, up to `batch` requests per
+    launch (igs_serve_batched), in FP64 and with FP32 cycles inside FP64
+    restarts.  Latency is completion minus arrival; throughput is requests
+    over the time to the last completion.  Every result's relative residual
+    is checked on the host with scipy (relres <= tol implies backward error
+    <= tol)."""
     import scipy.sparse as sp
     trace = W.serving_trace(count=count, seed=7)
 
-    def solve_bytes(q, iters):
+    def solve_bytes(q, iters, es):
         # algorithmic HBM bytes of `iters` Arnoldi iterations, cycles of
-        # `restart` columns: reduction 8n(j+2), update 8n(j+1) + 24n, operator
-        # apply 12 nnz + 4(n+1) + 16n at column j
+        # `restart` columns, basis elements of es bytes (8, or 4 in FP32
+        # cycles): reduction es n(j+2), update es n(j+1) + 3 es n, operator
+        # apply (4 + es) nnz + 4(n+1) + 2 es n at column j
         n, nnz = q.a.n, q.a.nnz
         full, rest = divmod(int(iters), restart)
         def cols(k):   # sum over j < k of the per-iteration bytes
-            return 16.0 * n * (k * (k - 1) / 2) + k * (8.0 * n * 3 + 24.0 * n + 12.0 * nnz
-                                                        + 4.0 * (n + 1) + 16.0 * n)
+            return 2.0 * es * n * (k * (k - 1) / 2) + k * (
+                es * n * 3 + 3.0 * es * n + (4.0 + es) * nnz + 4.0 * (n + 1) + 2.0 * es * n)
         return full * cols(restart) + cols(rest)
 
     systems = [(q.a, q.b, q.arrival) for q in trace]
     mats = [sp.csr_matrix((q.a.vals, q.a.col_idx, q.a.row_ptr), shape=(q.a.n, q.a.n)) for q in trace]
     out = {"workload": f"{W.SERVING.name}_{count}req_gmres{restart}_tol{tol:g}",
-           "requests": count, "slots": slots, "mem_cap_bytes": mem_cap,
+           "requests": count, "slots": slots, "batch": batch, "mem_cap_bytes": mem_cap,
            "n_range": [min(q.a.n for q in trace), max(q.a.n for q in trace)],
            "arrival_window_s": trace[-1].arrival}
-    for name, k, fp32 in (("fp64_serial", 1, 0), ("fp64_batched", slots, 0),
-                          ("fp32_cycles_batched", slots, 1)):
-        res, wall, rc = serve(systems, slots=k, mem_cap=mem_cap, restart=restart, tol=tol,
-                              gs_iters=2, inner_fp32=fp32, maxit=200000)
+    legs = (("fp64_serial", dict(slots=1), 0), ("fp64_streams", dict(slots=slots), 0),
+            ("fp64_batch_kernels", dict(batch=batch), 0),
+            ("fp32_cycles_batch_kernels", dict(batch=batch), 1))
+    for name, how, fp32 in legs:
+        res, wall, rc = serve(systems, mem_cap=mem_cap, restart=restart, tol=tol, gs_iters=2,
+                              inner_fp32=fp32, maxit=200000, **how)
         lat = np.array([r["t_done"] - r["arrival"] for r in res])
         rel = max(float(np.linalg.norm(q.b - A @ r["x"]) / np.linalg.norm(q.b))
                   for q, A, r in zip(trace, mats, res))
-        out[name] = {"slots": k, "rc": rc, "failed": sum(1 for r in res if r["rc"] != 0),
+        out[name] = {**how, "rc": rc, "failed": sum(1 for r in res if r["rc"] != 0),
                      "wall_s": wall, "solves_per_s": count / wall,
                      "iters_total": int(sum(r["iters"] for r in res)),
-                     "hbm_GBs_algorithmic": sum(solve_bytes(q, r["iters"])
+                     "hbm_GBs_algorithmic": sum(solve_bytes(q, r["iters"], 4.0 if fp32 else 8.0)
                                                 for q, r in zip(trace, res)) / wall / 1e9,
                      "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
                      "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
                      "max_relres": rel}
         log(f"[bench] serving {name}: {out[name]}")
     base = out["fp64_serial"]["solves_per_s"]
-    for name in ("fp64_batched", "fp32_cycles_batched"):
+    for name, _, _ in legs[1:]:
         out[name]["throughput_vs_fp64_serial"] = out[name]["solves_per_s"] / base
     return out
 
@@ -198,6 +203,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-batch", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -314,7 +320,8 @@ def main():
     if not args.no_serve:
         from paper_2205_07805_amd import serve
         log(f"[bench] serving {args.serve_requests} requests ...")
-        serving = serving_compare(W, serve, args.serve_requests, args.serve_slots)
+        serving = serving_compare(W, serve, args.serve_requests, args.serve_slots,
+                                  args.serve_batch)
 
     cpu = None
     if not args.no_cpu_baseline:
