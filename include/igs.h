@@ -109,6 +109,13 @@ typedef struct igs_opts {
   int batch_update_tiles; /* batches: at least this many 4-row-per-thread
                              tiles per block of the update.  1: the lone
                              grid; <= 0: 4                                   */
+  int cycle_graph;      /* 1: record the launches of a restart cycle in a HIP
+                           graph once and replay it for every cycle (one
+                           launch instead of 3(m+1)+4); the graph is kept in
+                           the context and reused while b, x and the settings
+                           stay the same.  Not with profile or two_reduce
+                           (ignored there).  Results are bit-identical.      */
+  int reserved2;
 } igs_opts;
 
 /* Result summary of a solve.  Any pointer argument of this type may be NULL. */

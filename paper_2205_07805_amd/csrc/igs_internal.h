@@ -110,6 +110,7 @@ __host__ __device__ inline int reduce_groups(int nb) { return nb < 8 ? nb : 8; }
 hipError_t launch_spmv(const Op& op, const double* u, double* z, const Ctl* gate, int j,
                        hipStream_t s);
 // Cycle start: reset the control block, then r = b - A x (FP64) into column 0
+// (its_before < 0: keep the value the host wrote into the control block)
 // of the basis (V, or V32 rounded to FP32 when w.fp32).
 hipError_t launch_residual(const Op& op, const double* b, const double* x, const Work& w,
                            long long its_before, long long maxit, int m, int gs, int final_v,

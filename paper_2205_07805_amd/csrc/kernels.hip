@@ -440,7 +440,7 @@ __device__ __forceinline__ void cycle_begin_body(Ctl* c, long long its_before, l
   c->status = kRunning;
   c->mode = kUpdNone;
   c->mode_iter = -1;
-  c->its_before = its_before;
+  if (its_before >= 0) c->its_before = its_before;   // < 0: the host wrote it
   c->maxit = maxit;
   c->m = m;
   c->gs = gs;

@@ -50,6 +50,20 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
+// What a recorded restart cycle depends on: buffers and settings baked into
+// its launches.  Zero-initialised, compared byte for byte.
+struct CycleKey {
+  const double* b;
+  const double* x;
+  const double* V;
+  const float* V32;
+  long long n, nnz;
+  long long maxit;
+  double tol, tau, cycle_rtol;
+  int m, gs, final_v, fp32;
+  int lpr, dense;
+};
+
 }  // namespace
 
 struct igs_ctx {
@@ -93,6 +107,11 @@ struct igs_ctx {
   std::vector<hipEvent_t> event_free;   // events ready for reuse
   std::vector<EventPair> pending;
   KStat stats[IGS_K_COUNT];
+
+  // a restart cycle recorded in a HIP graph (opts.cycle_graph)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t cycle_exec = nullptr;
+  CycleKey cycle_key{};
 
   std::string err;
 };
@@ -480,6 +499,8 @@ extern "C" int igs_destroy(igs_ctx* c) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->cycle_exec) (void)hipGraphExecDestroy(c->cycle_exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return IGS_OK;
 }
@@ -492,6 +513,36 @@ extern "C" int igs_solve(igs_ctx* c, const double* b, double* x, int restart, do
                          int gs_iters, igs_info* info) {
   return igs_solve_opts(c, b, x, restart, tol, gs_iters, nullptr, info);
 }
+
+namespace {
+
+// Record the launches `enqueue` makes into the context's cycle graph.
+template <typename F>
+int record_cycle(igs_ctx* c, F&& enqueue) {
+  if (!c->cap_stream)
+    HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  if (c->cycle_exec) {
+    (void)hipGraphExecDestroy(c->cycle_exec);
+    c->cycle_exec = nullptr;
+  }
+  c->cycle_key = CycleKey{};
+  HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue(c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  if (rc != IGS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HIP_OR_FAIL(c, e);
+  const hipError_t ie = hipGraphInstantiate(&c->cycle_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) c->cycle_exec = nullptr;
+  HIP_OR_FAIL(c, ie);
+  return IGS_OK;
+}
+
+}  // namespace
 
 extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restart, double tol,
                               int gs_iters, const igs_opts* opts, igs_info* info) {
@@ -562,49 +613,95 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   double relres = NAN, arn = NAN;
   bool converged = false;
   bool final_check = false;
-  while (true) {
-    const long long its_before = its;
-    const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
+  int cycles_timed = 0;   // the cycle index the profiling events carry
+  // The launches of one restart cycle on stream `st`: the residual, the
+  // iterations 0..jmax, then the least squares and x update.  A check cycle
+  // (after the iteration budget) runs iteration 0 only: the residual norm
+  // decides between convergence and giving up.  its_before < 0: the cycle
+  // takes the count the host wrote into the control block (graph replay).
+  auto enqueue_cycle = [&](hipStream_t st, long long its_before, long long maxit_cycle,
+                           bool check) -> int {
     {
-      Timed tm(c, pmask, IGS_K_RESIDUAL, -1, cycles, op64_bytes + es * dn);
+      Timed tm(c, pmask, IGS_K_RESIDUAL, -1, cycles_timed, op64_bytes + es * dn);
       HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w, its_before, maxit_cycle, m, gs_step,
-                                          final_v, tol, tau, cycle_rtol, s));
+                                          final_v, tol, tau, cycle_rtol, st));
     }
-    // A check cycle (after the iteration budget) runs iteration 0 only: the
-    // residual norm decides between convergence and giving up.
-    const int jmax = final_check ? 0 : m;
+    const int jmax = check ? 0 : m;
     for (int j = 0; j <= jmax; ++j) {
       if (j < m) {
-        Timed tm(c, pmask, IGS_K_SPMV, j, cycles, op_bytes);
+        Timed tm(c, pmask, IGS_K_SPMV, j, cycles_timed, op_bytes);
         if (fp32)
-          HIP_OR_FAIL(c, igs::launch_spmv32(c->op, w.V32 + (size_t)j * w.ldv, w.z32, w.ctl, j, s));
+          HIP_OR_FAIL(c, igs::launch_spmv32(c->op, w.V32 + (size_t)j * w.ldv, w.z32, w.ctl, j, st));
         else
-          HIP_OR_FAIL(c, igs::launch_spmv(c->op, w.V + (size_t)j * w.ldv, w.z, w.ctl, j, s));
+          HIP_OR_FAIL(c, igs::launch_spmv(c->op, w.V + (size_t)j * w.ldv, w.z, w.ctl, j, st));
       }
       int nb = 0;
       {
-        Timed tm(c, pmask, IGS_K_REDUCE, j, cycles, es * dn * (j + 1) + (j < m ? es * dn : 0.0));
-        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, s, &nb));
+        Timed tm(c, pmask, IGS_K_REDUCE, j, cycles_timed,
+                 es * dn * (j + 1) + (j < m ? es * dn : 0.0));
+        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, st, &nb));
       }
       // The update kernel runs the small solve of iteration j in every block.
       // The tail update (j = m) finishes the last column (and the lagged-norm
       // fallback there) and writes v_m on request; it never writes column
       // m + 1.
       {
-        Timed tm(c, pmask, IGS_K_UPDATE, j, cycles, es * dn * (j + 1) + 3.0 * es * dn);
-        HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_step, igs::reduce_groups(nb), s));
+        Timed tm(c, pmask, IGS_K_UPDATE, j, cycles_timed, es * dn * (j + 1) + 3.0 * es * dn);
+        HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_step, igs::reduce_groups(nb), st));
       }
-      if (two_reduce && j < m && !final_check) {
+      if (two_reduce && j < m && !check) {
         // second sweep on u_{j+1}: r2 = [V_{0:j+1}, u]^T u, then the correction
         int nb2 = 0;
-        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j + 1, false, s, &nb2));
-        HIP_OR_FAIL(c, igs::launch_correct(w, n, j + 1, igs::reduce_groups(nb2), s));
+        HIP_OR_FAIL(c, igs::launch_reduce(w, n, j + 1, false, st, &nb2));
+        HIP_OR_FAIL(c, igs::launch_correct(w, n, j + 1, igs::reduce_groups(nb2), st));
       }
     }
-    if (!final_check) {
-      HIP_OR_FAIL(c, igs::launch_lsq(w, m, s));
-      Timed tm(c, pmask, IGS_K_XUPDATE, -1, cycles, 0.0);
-      HIP_OR_FAIL(c, igs::launch_xupdate(w, n, x, s));
+    if (!check) {
+      HIP_OR_FAIL(c, igs::launch_lsq(w, m, st));
+      Timed tm(c, pmask, IGS_K_XUPDATE, -1, cycles_timed, 0.0);
+      HIP_OR_FAIL(c, igs::launch_xupdate(w, n, x, st));
+    }
+    return IGS_OK;
+  };
+  // Graph replay of the full cycles: recorded once (on a capture stream of
+  // the context, nothing runs while recording) for these settings and
+  // buffers, then launched on the solver's stream after the host writes the
+  // cycle's iteration count into the control block.
+  const bool graph_ok = o.cycle_graph != 0 && !prof && !two_reduce;
+  CycleKey key{};
+  key.b = b;
+  key.x = x;
+  key.V = w.V;
+  key.V32 = w.V32;
+  key.n = n;
+  key.nnz = c->nnz;
+  key.lpr = c->op.lpr;
+  key.dense = c->op.dense;
+  key.m = m;
+  key.gs = gs_step;
+  key.final_v = final_v;
+  key.fp32 = fp32 ? 1 : 0;
+  key.tol = tol;
+  key.tau = tau;
+  key.cycle_rtol = cycle_rtol;
+  key.maxit = maxit;
+  while (true) {
+    const long long its_before = its;
+    const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
+    cycles_timed = cycles;
+    if (graph_ok && !final_check) {
+      if (!c->cycle_exec || memcmp(&c->cycle_key, &key, sizeof(CycleKey)) != 0) {
+        rc = record_cycle(c, [&](hipStream_t st) { return enqueue_cycle(st, -1, maxit, false); });
+        if (rc != IGS_OK) return rc;
+        c->cycle_key = key;
+      }
+      c->h_ctl->its_before = its_before;
+      HIP_OR_FAIL(c, hipMemcpyAsync(&w.ctl->its_before, &c->h_ctl->its_before, sizeof(long long),
+                                    hipMemcpyHostToDevice, s));
+      HIP_OR_FAIL(c, hipGraphLaunch(c->cycle_exec, s));
+    } else {
+      rc = enqueue_cycle(s, its_before, maxit_cycle, final_check);
+      if (rc != IGS_OK) return rc;
     }
     HIP_OR_FAIL(c, hipMemcpyAsync(c->h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (prof) harvest(c, false);  // earlier cycles, while this one runs
