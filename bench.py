@@ -307,6 +307,17 @@ def main():
     two_reduce = {"iters": info2r["iters"], "seconds": dt2, "iters_per_s": info2r["iters"] / dt2,
                   "converged": bool(info2r["converged"])}
 
+    # Comparator: restarted GMRES on modified Gram-Schmidt Arnoldi (c + 2
+    # grid-wide reductions for column c), same system and tolerance.
+    rcm, infom = solve(2, mgs=1)
+    tm0 = time.perf_counter()
+    rcm, infom = solve(2, mgs=1)
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - tm0
+    mgs = {"iters": infom["iters"], "seconds": dtm, "iters_per_s": infom["iters"] / dtm,
+           "converged": bool(infom["converged"])}
+    log(f"[bench] mgs comparator: {mgs}")
+
     # The same solver family on the 96^3 system with GMRES(40), to backward
     # error 1e-14: FP64 cycles against FP32 cycles inside FP64 restarts.
     mixed = None
@@ -357,6 +368,7 @@ def main():
         "gs1": {"iters": info1["iters"], "seconds": dt1, "iters_per_s": info1["iters"] / dt1,
                 "converged": bool(info1["converged"])},
         "two_reduce_gs2": two_reduce,
+        "mgs_comparator": mgs,
         "mixed_precision": mixed,
         "serving": serving,
         "cpu_baseline": cpu,

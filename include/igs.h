@@ -115,7 +115,14 @@ typedef struct igs_opts {
                            the context and reused while b, x and the settings
                            stay the same.  Not with profile or two_reduce
                            (ignored there).  Results are bit-identical.      */
-  int reserved2;
+  int mgs;              /* 1: the comparator the paper measures against:
+                           restarted GMRES on modified Gram-Schmidt Arnoldi
+                           (Section 1), FP64, c + 2 grid-wide reductions for
+                           column c (one kernel each) where IGS-GMRES has one.
+                           gs_iters, lagnorm_tau and final_basis_vector do
+                           not apply; not with inner_fp32 or two_reduce
+                           (IGS_ENOTIMPL); profile and cycle_graph are
+                           ignored.                                           */
 } igs_opts;
 
 /* Result summary of a solve.  Any pointer argument of this type may be NULL. */

@@ -132,6 +132,13 @@ hipError_t launch_correct(const Work& w, long long n, int j, int ngroups, hipStr
 hipError_t launch_lsq(const Work& w, int m, hipStream_t s);
 hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s);
 
+// Modified Gram-Schmidt comparator (FP64): ||r0|| and v_0 = r0 / ||r0||;
+// then, after z = A v_c has been written to V[:, c+1], the c + 2 reductions
+// of column c and v_{c+1}.
+constexpr int kMgsMaxCols = 512;       // most columns of a cycle (the largest restart)
+hipError_t launch_mgs_start(const Work& w, long long n, hipStream_t s);
+hipError_t launch_mgs_column(const Work& w, long long n, int c, hipStream_t s);
+
 // Step kernels on caller buffers (no control block).
 hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j, const double* z,
                              double* part, double* gpart, int pstride, unsigned* tickets,

@@ -579,7 +579,7 @@ __device__ double givens_column(const Work& w, int c, double* col, const double*
 // Both grow by appending (a row of T, a column of H per iteration), so the
 // part an iteration reads is one contiguous prefix.
 __device__ __forceinline__ size_t tri_row(int i) { return (size_t)i * (i + 1) / 2; }
-__device__ __forceinline__ size_t hess_col(int c) { return (size_t)c * (c + 3) / 2; }
+__host__ __device__ __forceinline__ size_t hess_col(int c) { return (size_t)c * (c + 3) / 2; }
 
 // Copy count doubles from global src to shared dst with every thread's loads
 // issued in batches of eight (about one memory latency for the whole copy).
@@ -1898,6 +1898,176 @@ hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s) 
   else
     hipLaunchKernelGGL(xupdate_kernel<double>, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w,
                        n, x);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Comparator: modified Gram-Schmidt Arnoldi (the textbook GMRES the paper
+// measures IGS-GMRES against), FP64.  Column c takes w = A v_c in V[:, c+1],
+// then c + 2 kernels, each one grid-wide reduction: kernel i applies the
+// previous projection w -= H[i-1, c] v_{i-1} and forms H[i, c] = v_i^T w
+// (i <= c) or ||w||^2 (i = c + 1, whose last block finishes the column: the
+// Givens rotation, the breakdown and stopping tests), then v_{c+1} = w / H[c+1, c].
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kUpdateThreads) void mgs_kernel(Work w, long long n, int c, int i) {
+  __shared__ double red[kUpdateThreads / kWave];
+  __shared__ double tot[1];
+  __shared__ double scr[kUpdateThreads];
+  __shared__ double hcol[kMgsMaxCols + 2];
+  if (!ctl_runs(w.ctl, c)) return;
+  const Grid gr = hw_grid();
+  double* __restrict__ wv = w.V + (size_t)(c + 1) * w.ldv;
+  double* hc = w.H + hess_col(c);
+  const double hp = (i > 0) ? hc[i - 1] : 0.0;
+  const double* __restrict__ vp = w.V + (size_t)(i > 0 ? i - 1 : 0) * w.ldv;
+  const double* __restrict__ vi = w.V + (size_t)(i <= c ? i : 0) * w.ldv;
+  constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  double acc = 0.0;
+  for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
+#pragma unroll
+    for (int k = 0; k < kUpdateRows; ++k) {
+      const long long r = tile * kTile + (long long)k * kUpdateThreads + threadIdx.x;
+      if (r < n) {
+        double x = wv[r];
+        if (i > 0) x = fma(-hp, vp[r], x);
+        wv[r] = x;
+        acc = fma((i <= c) ? vi[r] : x, x, acc);
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int k = 0; k < kUpdateThreads / kWave; ++k) a += red[k];
+    w.part[(size_t)gr.bid * w.pstride] = a;
+  }
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 1, tot, scr, gr)) return;
+  const double total = tot[0];
+  if (i <= c) {
+    if (threadIdx.x == 0) hc[i] = total;
+    return;
+  }
+  // last block of the last kernel of column c: finish it
+  Ctl* ctl = w.ctl;
+  if (!isfinite(total)) {
+    if (threadIdx.x == 0) {
+      ctl->status = kNonfinite;
+      ctl->J = c;
+      ctl->end_iter = c;
+    }
+    return;
+  }
+  const double gamma = sqrt(total);
+  for (int q = threadIdx.x; q <= c; q += blockDim.x) hcol[q] = hc[q];
+  __shared__ double s_gc;
+  if (threadIdx.x == 0) s_gc = w.g[c];
+  __syncthreads();
+  const int brk = finish_column(w, c + 1, hcol, gamma, w.cs, w.sn, s_gc, n);
+  if (threadIdx.x == 0) {
+    int code = kRunning;
+    if (brk) code = kBreakdown;
+    else if (ctl->gabs <= ctl->tol_cyc) code = kConverged;
+    else if (c + 1 >= ctl->m) code = kFull;
+    else if (ctl->its_before + c + 1 >= ctl->maxit) code = kMaxit;
+    if (code != kRunning) {
+      ctl->status = code;
+      ctl->J = c + 1;
+      ctl->end_iter = c;
+      if (brk) ctl->breakdowns += 1;
+    }
+  }
+}
+
+// ||r0|| at the start of an MGS cycle (r0 in V[:, 0]); the last block sets
+// rho and g[0] and ends the cycle at once when it has converged or the
+// iteration budget is used up.
+__global__ __launch_bounds__(kUpdateThreads) void mgs_norm0_kernel(Work w, long long n) {
+  __shared__ double red[kUpdateThreads / kWave];
+  __shared__ double tot[1];
+  __shared__ double scr[kUpdateThreads];
+  const Grid gr = hw_grid();
+  const double* __restrict__ v = w.V;
+  constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  double acc = 0.0;
+  for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
+#pragma unroll
+    for (int k = 0; k < kUpdateRows; ++k) {
+      const long long r = tile * kTile + (long long)k * kUpdateThreads + threadIdx.x;
+      if (r < n) acc = fma(v[r], v[r], acc);
+    }
+  }
+  acc = wave_sum(acc);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int k = 0; k < kUpdateThreads / kWave; ++k) a += red[k];
+    w.part[(size_t)gr.bid * w.pstride] = a;
+  }
+  if (!grid_reduce_last(w.part, w.gpart, w.pstride, w.tickets, 1, tot, scr, gr)) return;
+  if (threadIdx.x != 0) return;
+  Ctl* ctl = w.ctl;
+  const double rho = sqrt(tot[0]);
+  ctl->rho = rho;
+  ctl->gabs = rho;
+  w.g[0] = rho;
+  if (!isfinite(rho)) {
+    ctl->status = kNonfinite;
+    ctl->J = 0;
+    ctl->end_iter = -1;
+  } else if (rho <= ctl->tol_abs || ctl->its_before >= ctl->maxit) {
+    ctl->status = (rho <= ctl->tol_abs) ? kConvStart : kMaxit;
+    ctl->J = 0;
+    ctl->end_iter = -1;
+  }
+}
+
+// V[:, col] /= *d while iteration gate_j runs and *d > 0.
+__global__ __launch_bounds__(kUpdateThreads) void mgs_scale_kernel(Work w, long long n, int col,
+                                                                 const double* d, int gate_j) {
+  if (!ctl_runs(w.ctl, gate_j)) return;
+  const double g = *d;
+  if (!(g > 0.0)) return;
+  double* __restrict__ v = w.V + (size_t)col * w.ldv;
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (long long)gridDim.x * blockDim.x)
+    v[r] = v[r] / g;
+}
+
+static unsigned mgs_grid(long long n) {
+  const long long per = (long long)kUpdateThreads * kUpdateRows;
+  long long g = (n + per - 1) / per;
+  const long long cap = resident_blocks(reinterpret_cast<const void*>(mgs_kernel), kUpdateThreads, 0);
+  if (g > cap) g = cap;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_mgs_start(const Work& w, long long n, hipStream_t s) {
+  const unsigned g = mgs_grid(n);
+  hipLaunchKernelGGL(mgs_norm0_kernel, dim3(g), dim3(kUpdateThreads), 0, s, w, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mgs_scale_kernel, dim3(g), dim3(kUpdateThreads), 0, s, w, n, 0,
+                     reinterpret_cast<const double*>(&w.ctl->rho), 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_mgs_column(const Work& w, long long n, int c, hipStream_t s) {
+  if (c + 1 > kMgsMaxCols) return hipErrorInvalidValue;
+  const unsigned g = mgs_grid(n);
+  for (int i = 0; i <= c + 1; ++i) {
+    hipLaunchKernelGGL(mgs_kernel, dim3(g), dim3(kUpdateThreads), 0, s, w, n, c, i);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(mgs_scale_kernel, dim3(g), dim3(kUpdateThreads), 0, s, w, n, c + 1,
+                     reinterpret_cast<const double*>(w.H + hess_col(c) + c + 1), c);
   return hipGetLastError();
 }
 

@@ -566,7 +566,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   if (rc != IGS_OK) return rc;
   const long long maxit = o.maxit > 0 ? o.maxit : 20 * n;
   const double tau = o.lagnorm_tau > 0.0 ? o.lagnorm_tau : 1e-4;
-  const bool prof = o.profile != 0;
+  const bool mgs = o.mgs != 0;
+  const bool prof = o.profile != 0 && !mgs;
   const int pmask = prof ? (o.profile_kernels ? o.profile_kernels : (1 << IGS_K_COUNT) - 1) : 0;
   const int final_v = o.final_basis_vector ? 1 : 0;
   const bool fp32 = o.inner_fp32 != 0;
@@ -575,6 +576,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   const bool two_reduce = o.two_reduce != 0 && gs_iters == 2;
   const int gs_step = two_reduce ? 1 : gs_iters;
   const double cycle_rtol = fp32 ? (o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5) : 0.0;
+  if (mgs && (fp32 || o.two_reduce))
+    return set_err(c, IGS_ENOTIMPL, "the MGS comparator is FP64 and one-pass only");
   if (fp32) {
     if (c->op.dense) return set_err(c, IGS_ENOTIMPL, "FP32 cycles need a CSR operator");
     if (o.keep_first_basis)
@@ -621,6 +624,22 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   // takes the count the host wrote into the control block (graph replay).
   auto enqueue_cycle = [&](hipStream_t st, long long its_before, long long maxit_cycle,
                            bool check) -> int {
+    if (mgs) {
+      // modified Gram-Schmidt: v_0 = r0 / ||r0||, then per column c the
+      // operator apply into V[:, c+1] and c + 2 reductions
+      HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w, its_before, maxit_cycle, m, 1, 0, tol,
+                                          tau, 0.0, st));
+      HIP_OR_FAIL(c, igs::launch_mgs_start(w, n, st));
+      if (check) return IGS_OK;
+      for (int col = 0; col < m; ++col) {
+        HIP_OR_FAIL(c, igs::launch_spmv(c->op, w.V + (size_t)col * w.ldv,
+                                        w.V + (size_t)(col + 1) * w.ldv, w.ctl, col, st));
+        HIP_OR_FAIL(c, igs::launch_mgs_column(w, n, col, st));
+      }
+      HIP_OR_FAIL(c, igs::launch_lsq(w, m, st));
+      HIP_OR_FAIL(c, igs::launch_xupdate(w, n, x, st));
+      return IGS_OK;
+    }
     {
       Timed tm(c, pmask, IGS_K_RESIDUAL, -1, cycles_timed, op64_bytes + es * dn);
       HIP_OR_FAIL(c, igs::launch_residual(c->op, b, x, w, its_before, maxit_cycle, m, gs_step,
@@ -667,7 +686,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   // the context, nothing runs while recording) for these settings and
   // buffers, then launched on the solver's stream after the host writes the
   // cycle's iteration count into the control block.
-  const bool graph_ok = o.cycle_graph != 0 && !prof && !two_reduce;
+  const bool graph_ok = o.cycle_graph != 0 && !prof && !two_reduce && !mgs;
   CycleKey key{};
   key.b = b;
   key.x = x;

@@ -36,7 +36,7 @@ class IgsOpts(ctypes.Structure):
                 ("profile_kernels", c_int), ("inner_fp32", c_int), ("two_reduce", c_int),
                 ("reserved", c_int * 1),
                 ("inner_rtol", c_double), ("batch_reduce_rows", c_int),
-                ("batch_update_tiles", c_int), ("cycle_graph", c_int), ("reserved2", c_int)]
+                ("batch_update_tiles", c_int), ("cycle_graph", c_int), ("mgs", c_int)]
 
 
 class IgsInfo(ctypes.Structure):
