@@ -289,6 +289,37 @@ int igs_solve_batch(igs_ctx *const *ctxs, const double *const *b, double *const 
 int igs_serve_batched(igs_request *reqs, int nreq, int batch, int64_t mem_cap, int restart,
                       double tol, int gs_iters, const igs_opts *opts, double *wall_seconds);
 
+/* ---- Autotuning of launch shapes ---------------------------------------- */
+
+typedef struct igs_tune_report {
+  double cycle_ms_before;  /* one full restart cycle with the default shapes  */
+  double cycle_ms_after;   /* the same with the chosen shapes                  */
+  int spmv_rpg;            /* rows per lane group of the operator apply (0:
+                              the default kept)                               */
+  int reduce_halved;       /* iterations j whose fused reduction runs with
+                              half the blocks (twice the rows per block)      */
+  int update_halved;       /* the same for the basis update                  */
+  int reserved;
+} igs_tune_report;
+
+/*
+ * Choose launch shapes for this context by timing them on the device: two
+ * full restart cycles of GMRES(restart) with gs_iters sweeps (tol 0, a fixed
+ * right-hand side, HIP events around every launch) per candidate.  The
+ * candidates are, per iteration j, the fused reduction and the update with
+ * half their default blocks (kept where they save more than 3%), and for a
+ * CSR operator the rows per lane group of the operator apply.  The choice
+ * stays in the context and applies to every later igs_solve_opts on it; the
+ * results change by summation order only (the grid of the reductions
+ * changes), and stay deterministic.  Takes a few cycles of device time;
+ * allocates and frees two vectors of n doubles.  The profile counters are
+ * reset.  report may be NULL.  Errors: IGS_EINVAL, IGS_ENOMEM, IGS_EDEVICE.
+ */
+int igs_tune(igs_ctx *ctx, int restart, int gs_iters, igs_tune_report *report);
+
+/* Back to the default launch shapes. */
+int igs_tune_reset(igs_ctx *ctx);
+
 /* ---- Inspection of the FIRST restart cycle of the last solve (tests) ----- */
 
 /* Copy the Hessenberg matrix H (before Givens rotation) of the first cycle to

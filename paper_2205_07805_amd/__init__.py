@@ -9,7 +9,7 @@ from .igs import (IgsError, IgsInfo, IgsOpts, IgsRequest, igs_create, igs_create
                   igs_debug_copy_H, igs_debug_copy_V, igs_destroy, igs_kernel_reduce, igs_kernel_spmv,
                   igs_kernel_update, igs_last_error, igs_profile_get, igs_profile_reset,
                   igs_serve, igs_serve_batched, igs_solve, igs_solve_batch, igs_solve_opts,
-                  load_library)
+                  igs_tune, igs_tune_reset, load_library)
 from .serving import serve
 from .solver import Solver, solve_batch
 
@@ -18,5 +18,6 @@ __all__ = [
     "igs_create", "igs_create_dense", "igs_solve", "igs_solve_opts", "igs_destroy",
     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
     "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
-    "igs_serve", "igs_solve_batch", "igs_serve_batched", "solve_batch",
+    "igs_serve", "igs_solve_batch", "igs_serve_batched", "solve_batch", "igs_tune",
+    "igs_tune_reset",
 ]

@@ -76,6 +76,7 @@ struct Op {
   long long lda;
   int lpr;             // CSR lanes per row
   const float* vals32; // CSR values rounded to FP32 (mixed precision; may be null)
+  int rpg;             // CSR rows per lane group (0: the default for lpr; set by the tuner)
 };
 
 // Device workspace of a context (all device pointers).
@@ -98,6 +99,10 @@ struct Work {
   float* V32;                    // FP32 basis (mixed precision), same ldv
   float* z32;                    // FP32 A u
   int fp32;                      // 1: the step kernels work on V32 / z32
+  // Host memory, read by the launchers only (null: the default grids): for
+  // iteration j, bit 0 halves the blocks of the fused reduction and bit 1
+  // those of the update (each block then takes twice the rows).
+  const unsigned char* tune;
 };
 
 // Groups of the first level of the deterministic grid reduction for a grid

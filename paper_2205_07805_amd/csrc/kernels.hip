@@ -359,8 +359,7 @@ template <> __host__ __device__ const float* op_vals<float>(const Op& op) { retu
 // lane group RPG: up to 4 rows while a group is at most 8 lanes wide.
 static int spmv_rpg(int lpr) { return lpr <= 8 ? (LPR_RPG_MAX) : (lpr == 16 ? 2 : 1); }
 
-static unsigned spmv_grid(long long n, int lpr) {
-  const int rpg = spmv_rpg(lpr);
+static unsigned spmv_grid(long long n, int lpr, int rpg) {
   const long long groups = (n + rpg - 1) / rpg;
   const long long threads = groups * lpr;
   unsigned grid = (unsigned)((threads + 255) / 256);
@@ -385,15 +384,19 @@ static hipError_t op_apply(const Op& op, const TA* x, TY* y, const TA* bsub, con
   const TA* vals = op_vals<TA>(op);
   if (vals == nullptr) return hipErrorInvalidValue;
   const int lpr = op.lpr;
-  const unsigned grid = spmv_grid(op.n, lpr);
-  switch (lpr) {
+  const int rpg = op.rpg > 0 ? op.rpg : spmv_rpg(lpr);
+  const unsigned grid = spmv_grid(op.n, lpr, rpg);
+  switch (lpr * 8 + rpg) {
 #define IGS_SPMV_CASE(L, R)                                                                     \
-  case L:                                                                                       \
+  case L * 8 + R:                                                                               \
     hipLaunchKernelGGL((spmv_csr_kernel<L, R, TA, TY>), dim3(grid), dim3(256), 0, s, op.n,      \
                        op.row_ptr, op.col_idx, vals, x, y, bsub, gate, gate_j);                 \
     break;
-    IGS_SPMV_CASE(1, LPR_RPG_MAX) IGS_SPMV_CASE(2, LPR_RPG_MAX) IGS_SPMV_CASE(4, LPR_RPG_MAX)
-    IGS_SPMV_CASE(8, LPR_RPG_MAX) IGS_SPMV_CASE(16, 2) IGS_SPMV_CASE(32, 1) IGS_SPMV_CASE(64, 1)
+    IGS_SPMV_CASE(1, 1) IGS_SPMV_CASE(1, 2) IGS_SPMV_CASE(1, 4)
+    IGS_SPMV_CASE(2, 1) IGS_SPMV_CASE(2, 2) IGS_SPMV_CASE(2, 4)
+    IGS_SPMV_CASE(4, 1) IGS_SPMV_CASE(4, 2) IGS_SPMV_CASE(4, 4)
+    IGS_SPMV_CASE(8, 1) IGS_SPMV_CASE(8, 2) IGS_SPMV_CASE(8, 4)
+    IGS_SPMV_CASE(16, 1) IGS_SPMV_CASE(16, 2) IGS_SPMV_CASE(32, 1) IGS_SPMV_CASE(64, 1)
 #undef IGS_SPMV_CASE
     default: return hipErrorInvalidValue;
   }
@@ -1357,6 +1360,7 @@ static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z
     const int cus = resident_blocks(nullptr, 0, 0);
     if (cap > cus) cap = cus;
   }
+  if (w.tune && (w.tune[j] & 1) && cap > 1) cap /= 2;
   reduce_rows(sh, n, cap);
   if (nblocks_out) *nblocks_out = sh.nblocks;
   Work wa = w;
@@ -1739,8 +1743,8 @@ static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t,
   UpdateKernel<T> k = has_t ? (vec ? update_kernel<true, true, T> : update_kernel<true, false, T>)
                             : (vec ? update_kernel<false, true, T> : update_kernel<false, false, T>);
   const size_t lds = update_lds_doubles(j) * sizeof(double);
-  const unsigned grid =
-      update_grid(reinterpret_cast<const void*>(k), n, update_tile_rows<T>(), lds);
+  unsigned grid = update_grid(reinterpret_cast<const void*>(k), n, update_tile_rows<T>(), lds);
+  if (raw == 0 && w.tune && (w.tune[j] & 2) && grid > 1) grid = (grid + 1) / 2;
   Work wa = w;
   long long na = n, ldva = ldv_raw;
   int ja = j, nga = ngroups, rawa = raw;
@@ -2259,7 +2263,7 @@ static hipError_t batch_spmv_lpr(const BatchRun& r, int j) {
     for (int q = 0; q < r.count; ++q) {
       const Inst& I = r.h_tab[r.act[q]];
       if (I.op.lpr != lpr) continue;
-      nb[sub.count] = (int)spmv_grid(I.n, lpr);
+      nb[sub.count] = (int)spmv_grid(I.n, lpr, spmv_rpg(lpr));
       sub.act[sub.count++] = r.act[q];
     }
     BatchMap m;

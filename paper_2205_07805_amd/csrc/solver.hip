@@ -62,6 +62,7 @@ struct CycleKey {
   double tol, tau, cycle_rtol;
   int m, gs, final_v, fp32;
   int lpr, dense;
+  int rpg, tune_gen;
 };
 
 }  // namespace
@@ -107,6 +108,12 @@ struct igs_ctx {
   std::vector<hipEvent_t> event_free;   // events ready for reuse
   std::vector<EventPair> pending;
   KStat stats[IGS_K_COUNT];
+
+  KStat stats_j[IGS_K_COUNT][IGS_MAX_RESTART + 1];   // the same per iteration j
+
+  // launch shapes chosen by igs_tune (empty: the defaults)
+  std::vector<unsigned char> tune;
+  int tune_gen = 0;
 
   // a restart cycle recorded in a HIP graph (opts.cycle_graph)
   hipStream_t cap_stream = nullptr;
@@ -333,6 +340,12 @@ void harvest(igs_ctx* c, bool wait) {
         s.launches += 1;
         s.ms += ms;
         s.bytes += p.bytes;
+        if (p.j >= 0 && p.j <= IGS_MAX_RESTART) {
+          KStat& sj = c->stats_j[p.kernel][p.j];
+          sj.launches += 1;
+          sj.ms += ms;
+          sj.bytes += p.bytes;
+        }
       }
     }
     c->event_free.push_back(p.a);
@@ -587,6 +600,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   }
   Work& w = c->w;
   w.fp32 = fp32 ? 1 : 0;
+  w.tune = c->tune.empty() ? nullptr : c->tune.data();
   hipStream_t s = c->stream;
   c->J_first = -1;
   c->V_first_valid = 0;
@@ -696,6 +710,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   key.nnz = c->nnz;
   key.lpr = c->op.lpr;
   key.dense = c->op.dense;
+  key.rpg = c->op.rpg;
+  key.tune_gen = c->tune_gen;
   key.m = m;
   key.gs = gs_step;
   key.final_v = final_v;
@@ -891,6 +907,135 @@ extern "C" int igs_profile_reset(igs_ctx* c) {
   if (!c) return IGS_EINVAL;
   harvest(c, true);
   for (KStat& s : c->stats) s = KStat{};
+  for (auto& row : c->stats_j)
+    for (KStat& s : row) s = KStat{};
+  return IGS_OK;
+}
+
+// ===========================================================================
+// Autotuning of launch shapes
+// ===========================================================================
+
+extern "C" int igs_tune_reset(igs_ctx* c) {
+  if (!c) return IGS_EINVAL;
+  c->tune.clear();
+  c->op.rpg = 0;
+  c->tune_gen += 1;
+  return IGS_OK;
+}
+
+extern "C" int igs_tune(igs_ctx* c, int restart, int gs_iters, igs_tune_report* rep) {
+  if (!c) return IGS_EINVAL;
+  c->err.clear();
+  if (restart < 1 || (gs_iters != 1 && gs_iters != 2))
+    return set_err(c, IGS_EINVAL, "restart >= 1 and gs_iters in {1, 2}");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const long long n = c->n;
+  const int m = (int)std::min<long long>(std::min<long long>(restart, n), IGS_MAX_RESTART);
+  double* b = nullptr;
+  double* x = nullptr;
+  if (dalloc(&b, n) != hipSuccess || dalloc(&x, n) != hipSuccess) {
+    if (b) (void)hipFree(b);
+    return set_err(c, IGS_ENOMEM, "cannot allocate the tuning vectors");
+  }
+  {
+    // a right-hand side with no special structure: b_i = 1 + (i mod 7) / 7
+    std::vector<double> hb(n);
+    for (long long i = 0; i < n; ++i) hb[i] = 1.0 + (double)(i % 7) / 7.0;
+    if (hipMemcpy(b, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(b);
+      (void)hipFree(x);
+      return set_err(c, IGS_EDEVICE, "cannot copy the tuning right-hand side");
+    }
+  }
+  std::vector<double> red(m + 1), upd(m + 1);
+  double spmv_ms = 0.0, total_ms = 0.0;
+  // two full cycles (tol 0) with every launch timed; per-iteration totals
+  auto measure = [&]() -> int {
+    igs_profile_reset(c);
+    HIP_OR_FAIL(c, hipMemsetAsync(x, 0, sizeof(double) * n, c->stream));
+    igs_opts o{};
+    o.profile = 1;
+    o.max_cycles = 2;
+    igs_info info{};
+    const int rc = igs_solve_opts(c, b, x, restart, 0.0, gs_iters, &o, &info);
+    if (rc < 0) return rc;
+    harvest(c, true);
+    total_ms = 0.0;
+    for (int k = 0; k < IGS_K_COUNT; ++k) total_ms += c->stats[k].ms;
+    spmv_ms = c->stats[IGS_K_SPMV].ms;
+    for (int j = 0; j <= m; ++j) {
+      red[j] = c->stats_j[IGS_K_REDUCE][j].ms;
+      upd[j] = c->stats_j[IGS_K_UPDATE][j].ms;
+    }
+    return IGS_OK;
+  };
+  int rc = IGS_OK;
+  igs_tune_reset(c);
+  rc = measure();
+  const double before = total_ms;
+  const std::vector<double> red0 = red, upd0 = upd;
+  int red_half = 0, upd_half = 0, best_rpg = 0;
+  if (rc == IGS_OK) {
+    // every iteration with half the blocks, then keep the halving where it
+    // saved more than 3%
+    c->tune.assign(IGS_MAX_RESTART + 1, 3);
+    c->tune_gen += 1;
+    rc = measure();
+  }
+  if (rc == IGS_OK) {
+    std::vector<unsigned char> t(IGS_MAX_RESTART + 1, 0);
+    for (int j = 0; j <= m; ++j) {
+      if (red[j] > 0.0 && red[j] < 0.97 * red0[j]) { t[j] |= 1; ++red_half; }
+      if (upd[j] > 0.0 && upd[j] < 0.97 * upd0[j]) { t[j] |= 2; ++upd_half; }
+    }
+    c->tune = t;
+    c->tune_gen += 1;
+    if (red_half + upd_half == 0) c->tune.clear();
+  }
+  if (rc == IGS_OK && !c->op.dense) {
+    // rows per lane group of the operator apply
+    const int lpr = c->op.lpr;
+    const int cands[3] = {1, 2, 4};
+    const int maxr = lpr <= 8 ? 4 : (lpr == 16 ? 2 : 1);
+    c->op.rpg = 0;
+    c->tune_gen += 1;
+    rc = measure();
+    double best = spmv_ms;
+    for (int q = 0; q < 3 && rc == IGS_OK; ++q) {
+      const int r = cands[q];
+      if (r > maxr || r == (lpr <= 8 ? 4 : (lpr == 16 ? 2 : 1))) continue;   // the default
+      c->op.rpg = r;
+      c->tune_gen += 1;
+      rc = measure();
+      if (rc == IGS_OK && spmv_ms < 0.97 * best) {
+        best = spmv_ms;
+        best_rpg = r;
+      }
+    }
+    c->op.rpg = best_rpg;
+    c->tune_gen += 1;
+  }
+  double after = 0.0;
+  if (rc == IGS_OK) {
+    rc = measure();
+    after = total_ms;
+  }
+  igs_profile_reset(c);
+  (void)hipFree(b);
+  (void)hipFree(x);
+  if (rc != IGS_OK) {
+    igs_tune_reset(c);
+    return rc;
+  }
+  if (rep) {
+    rep->cycle_ms_before = before / 2.0;
+    rep->cycle_ms_after = after / 2.0;
+    rep->spmv_rpg = best_rpg;
+    rep->reduce_halved = red_half;
+    rep->update_halved = upd_half;
+    rep->reserved = 0;
+  }
   return IGS_OK;
 }
 

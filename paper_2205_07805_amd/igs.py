@@ -26,7 +26,7 @@ EXPORTED = (
     "igs_create", "igs_create_dense", "igs_solve", "igs_solve_opts", "igs_destroy",
     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
     "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
-    "igs_serve", "igs_solve_batch", "igs_serve_batched",
+    "igs_serve", "igs_solve_batch", "igs_serve_batched", "igs_tune", "igs_tune_reset",
 )
 
 
@@ -57,6 +57,12 @@ class IgsRequest(ctypes.Structure):
                 ("vals", c_void_p), ("b", c_void_p), ("x", c_void_p), ("arrival", c_double),
                 ("t_admit", c_double), ("t_done", c_double), ("iters", c_int64), ("rc", c_int),
                 ("status", c_int)]
+
+
+class IgsTuneReport(ctypes.Structure):
+    _fields_ = [("cycle_ms_before", c_double), ("cycle_ms_after", c_double),
+                ("spmv_rpg", c_int), ("reduce_halved", c_int), ("update_halved", c_int),
+                ("reserved", c_int)]
 
 
 class IgsError(RuntimeError):
@@ -98,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                     c_int, POINTER(IgsOpts), POINTER(IgsInfo), POINTER(c_int)]),
         "igs_serve_batched": (c_int, [POINTER(IgsRequest), c_int, c_int, c_int64, c_int, c_double,
                                       c_int, POINTER(IgsOpts), POINTER(c_double)]),
+        "igs_tune": (c_int, [P, c_int, c_int, POINTER(IgsTuneReport)]),
+        "igs_tune_reset": (c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -249,3 +257,15 @@ def igs_serve_batched(reqs, batch, mem_cap, restart, tol, gs_iters, opts: IgsOpt
                                           ctypes.byref(opts) if opts else None, ctypes.byref(wall))
     _check("igs_serve_batched", rc, None)
     return rc, wall.value
+
+
+def igs_tune(ctx, restart, gs_iters=2) -> dict:
+    """Choose launch shapes for ctx on the device; returns the report."""
+    rep = IgsTuneReport()
+    rc = load_library().igs_tune(ctx, int(restart), int(gs_iters), ctypes.byref(rep))
+    _check("igs_tune", rc, ctx)
+    return {name: getattr(rep, name) for name, _ in rep._fields_ if name != "reserved"}
+
+
+def igs_tune_reset(ctx) -> None:
+    _check("igs_tune_reset", load_library().igs_tune_reset(ctx), ctx)

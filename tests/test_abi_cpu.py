@@ -59,6 +59,7 @@ int main(void) {
   printf("%d %d\n", IGS_MAX_RESTART, IGS_K_COUNT);
   printf("%zu %zu\n", offsetof(igs_opts, inner_fp32), offsetof(igs_opts, inner_rtol));
   printf("%zu\n", offsetof(igs_opts, batch_update_tiles));
+  printf("%zu %zu\n", sizeof(igs_tune_report), offsetof(igs_tune_report, update_halved));
   printf("%zu %zu %zu %zu %zu\n", sizeof(igs_request), offsetof(igs_request, arrival),
          offsetof(igs_request, iters), offsetof(igs_request, rc), offsetof(igs_request, status));
   return 0;
@@ -78,10 +79,12 @@ int main(void) {
     assert vals[5] == igs.IGS_MAX_RESTART and vals[6] == igs.IGS_K_COUNT
     assert vals[7] == IgsOpts.inner_fp32.offset and vals[8] == IgsOpts.inner_rtol.offset
     assert vals[9] == IgsOpts.batch_update_tiles.offset
-    from paper_2205_07805_amd.igs import IgsRequest
-    assert vals[10] == ctypes.sizeof(IgsRequest) and vals[11] == IgsRequest.arrival.offset
-    assert vals[12] == IgsRequest.iters.offset and vals[13] == IgsRequest.rc.offset
-    assert vals[14] == IgsRequest.status.offset
+    from paper_2205_07805_amd.igs import IgsRequest, IgsTuneReport
+    assert vals[10] == ctypes.sizeof(IgsTuneReport)
+    assert vals[11] == IgsTuneReport.update_halved.offset
+    assert vals[12] == ctypes.sizeof(IgsRequest) and vals[13] == IgsRequest.arrival.offset
+    assert vals[14] == IgsRequest.iters.offset and vals[15] == IgsRequest.rc.offset
+    assert vals[16] == IgsRequest.status.offset
 
 
 def test_missing_library_fails_loudly(tmp_path):
