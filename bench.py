@@ -131,6 +131,46 @@ def mixed_precision_compare(torch, W, Solver, igs, dev, steps, grid=96, restart=
     return out
 
 
+def other_configs(torch, W, Solver, igs, steps=5):
+    """The two other single-solve configurations, timed the same way as the
+    bench line: the small 2D system (n = 1,024, GMRES(50), tol 1e-12; also
+    with its cycles replayed from a HIP graph), and one full GMRES(200) cycle
+    on the dense non-normal n = 4,096 matrix (tol 0)."""
+    out = {}
+    cases = (("convdiff2d_N32_Pe10_gmres50_tol1e-12", W.make_convdiff2d_32, 50, 1e-12, {}),
+             ("convdiff2d_N32_Pe10_gmres50_tol1e-12_graph", W.make_convdiff2d_32, 50, 1e-12,
+              {"cycle_graph": 1}),
+             ("dense_nonnormal_n4096_gmres200_one_cycle", W.make_dense_nonnormal, 200, 0.0,
+              {"max_cycles": 1}))
+    for name, make, restart, tol, opts in cases:
+        a, b = make()
+        stream = torch.cuda.Stream()
+        s = Solver(a, stream=stream)
+        try:
+            bd = s.to_device(b)
+            x = torch.zeros_like(bd)
+            o = igs.IgsOpts(**opts)
+
+            def one():
+                with torch.cuda.stream(stream):
+                    x.zero_()
+                    return igs.igs_solve_opts(s.ctx, bd, x, restart, tol, 2, o)
+            one()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rc, info = one()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            out[name] = {"n": int(len(b)), "rc": rc, "iters": info["iters"],
+                         "ms_per_solve": 1e3 * dt, "iters_per_s": info["iters"] / dt,
+                         "us_per_iter": 1e6 * dt / max(info["iters"], 1),
+                         "relres_true": info["relres_true"]}
+        finally:
+            s.close()
+    return out
+
+
 def serving_compare(W, serve, count, slots, batch, mem_cap=64 << 30, restart=50, tol=1e-12):
     """The serving trace (2D convection-diffusion, sides uniform on [32, 512],
     Pe uniform on [1, 100], Poisson arrivals at 200/s, b seeded per request)
@@ -327,6 +367,9 @@ def main():
         log(f"[bench] mixed: {mixed}")
     s.close()
 
+    others = other_configs(torch, W, Solver, igs)
+    log(f"[bench] other configurations: {others}")
+
     serving = None
     if not args.no_serve:
         from paper_2205_07805_amd import serve
@@ -370,6 +413,7 @@ def main():
         "two_reduce_gs2": two_reduce,
         "mgs_comparator": mgs,
         "mixed_precision": mixed,
+        "other_configs": others,
         "serving": serving,
         "cpu_baseline": cpu,
         "profiled": not args.no_profile,
