@@ -77,6 +77,13 @@ struct Op {
   int lpr;             // CSR lanes per row
   const float* vals32; // CSR values rounded to FP32 (mixed precision; may be null)
   int rpg;             // CSR rows per lane group (0: the default for lpr; set by the tuner)
+  // The same matrix in column-major ELL form (rows of at most 8 entries,
+  // lpr == 8): entry k of row r at k * n + r, padded with (column 0, value
+  // 0); ell_k = 0 when absent.  Its product is bit-identical to the CSR one.
+  int ell_k;
+  const int* ell_col;
+  const double* ell_val;
+  const float* ell_val32;
 };
 
 // Device workspace of a context (all device pointers).

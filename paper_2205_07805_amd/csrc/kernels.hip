@@ -351,9 +351,45 @@ __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const doub
   if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
 }
 
+// The operator apply from the ELL form, one row per thread: the same
+// products and the same order of additions as the CSR kernel with 8 lanes
+// per row (pairs, then quads, then the two halves; entries past the row's
+// end contribute 0 * x[0]), with no fused multiply-adds (contraction off),
+// so z is bit-identical to the CSR kernel's; one memory latency less (no row
+// bounds to load first).
+template <int K, typename TA, typename TY>
+__global__ __launch_bounds__(256) void spmv_ell_kernel(long long n, const int* __restrict__ col,
+                                                       const TA* __restrict__ val,
+                                                       const TA* __restrict__ x,
+                                                       TY* __restrict__ y,
+                                                       const TA* __restrict__ bsub,
+                                                       const Ctl* __restrict__ gate, int gate_j) {
+#pragma clang fp contract(off)
+  const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gate != nullptr && load_agent(&gate->end_iter) < gate_j) return;
+  if (row >= n) return;
+  int c[8];
+  TA v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    c[k] = k < K ? col[(long long)k * n + row] : 0;
+    v[k] = k < K ? val[(long long)k * n + row] : TA(0);
+  }
+  TA p[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) p[k] = v[k] * x[c[k]];
+  const TA q0 = (p[0] + p[1]) + (p[2] + p[3]);
+  const TA q1 = (p[4] + p[5]) + (p[6] + p[7]);
+  const TA acc = q0 + q1;
+  y[row] = (TY)((bsub != nullptr) ? bsub[row] - acc : acc);
+}
+
 template <typename TA> __host__ __device__ const TA* op_vals(const Op& op);
 template <> __host__ __device__ const double* op_vals<double>(const Op& op) { return op.vals; }
 template <> __host__ __device__ const float* op_vals<float>(const Op& op) { return op.vals32; }
+template <typename TA> const TA* ell_vals(const Op& op);
+template <> const double* ell_vals<double>(const Op& op) { return op.ell_val; }
+template <> const float* ell_vals<float>(const Op& op) { return op.ell_val32; }
 
 // Lanes per row LPR (a power of two near the mean row length) and rows per
 // lane group RPG: up to 4 rows while a group is at most 8 lanes wide.
@@ -380,6 +416,23 @@ static hipError_t op_apply(const Op& op, const TA* x, TY* y, const TA* bsub, con
     } else {
       return hipErrorInvalidValue;   // the dense operator is FP64 only
     }
+  }
+  if (op.ell_k > 0 && op.rpg == 0) {
+    const TA* ev = ell_vals<TA>(op);
+    if (ev == nullptr) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((op.n + 255) / 256);
+    switch (op.ell_k) {
+#define IGS_ELL_CASE(K)                                                                         \
+  case K:                                                                                       \
+    hipLaunchKernelGGL((spmv_ell_kernel<K, TA, TY>), dim3(grid), dim3(256), 0, s, op.n,         \
+                       op.ell_col, ev, x, y, bsub, gate, gate_j);                               \
+    break;
+      IGS_ELL_CASE(1) IGS_ELL_CASE(2) IGS_ELL_CASE(3) IGS_ELL_CASE(4)
+      IGS_ELL_CASE(5) IGS_ELL_CASE(6) IGS_ELL_CASE(7) IGS_ELL_CASE(8)
+#undef IGS_ELL_CASE
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
   }
   const TA* vals = op_vals<TA>(op);
   if (vals == nullptr) return hipErrorInvalidValue;

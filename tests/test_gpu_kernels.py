@@ -166,3 +166,52 @@ def test_update_matches_oracle(torch, n, j, pad):
     # untouched: the other columns and the padding
     np.testing.assert_array_equal(out[:j, :n], Vt[:j])
     assert np.all(out[:, n:] == 0.0)
+
+
+@pytest.mark.parametrize("case", ["convdiff2d_31", "convdiff3d_17"])
+def test_ell_form_is_bit_identical_to_csr(torch, case):
+    """Short-row operators also keep a column-major ELL form; its product
+    must equal the CSR kernel's bit for bit.  A copy of the matrix with four
+    explicit zeros appended to one row (9 entries, so no ELL form) runs the
+    CSR kernel; every other row must agree exactly, with and without the
+    subtracted right-hand side (the residual b - A x of a cycle start)."""
+    from paper_2205_07805_amd import Solver, igs
+    a = CSR_CASES[case]()
+    n = a.n
+    rp = a.row_ptr.astype(np.int64)
+    r = n // 2
+    s0, s1 = rp[r], rp[r + 1]
+    used = set(a.col_idx[s0:s1].tolist())
+    extra = np.array([c for c in range(n) if c not in used][:4], dtype=np.int32)
+    ci2 = np.concatenate([a.col_idx[:s1], extra, a.col_idx[s1:]]).astype(np.int32)
+    va2 = np.concatenate([a.vals[:s1], np.zeros(4), a.vals[s1:]])
+    rp2 = rp.copy()
+    rp2[r + 1:] += 4
+    b2 = W.Csr(n, rp2.astype(np.int32), ci2, va2)
+    print(f"ELL against CSR {case} n={n}", flush=True)
+    ctx_e = _ctx_csr(a)
+    ctx_c = _ctx_csr(b2)
+    try:
+        u = torch.tensor(W.rhs_normal(n, 3), device="cuda")
+        ze = torch.empty_like(u)
+        zc = torch.empty_like(u)
+        igs.igs_kernel_spmv(ctx_e, u, ze)
+        igs.igs_kernel_spmv(ctx_c, u, zc)
+        mask = np.ones(n, bool)
+        mask[r] = False
+        assert np.array_equal(ze.cpu().numpy()[mask], zc.cpu().numpy()[mask])
+    finally:
+        igs.igs_destroy(ctx_e)
+        igs.igs_destroy(ctx_c)
+    # whole solves (residuals with a nonzero x0 included): the row with the
+    # explicit zeros sums the same products, so the solves agree exactly
+    b = W.rhs_normal(n, 4)
+    x0 = W.rhs_normal(n, 5)
+    se, sc = Solver(a), Solver(b2)
+    try:
+        xe, rce, ie = se.solve(b, x0=x0, restart=20, tol=1e-12)
+        xc, rcc, ic = sc.solve(b, x0=x0, restart=20, tol=1e-12)
+        assert ie["iters"] == ic["iters"] and np.array_equal(xe.cpu().numpy(), xc.cpu().numpy())
+    finally:
+        se.close()
+        sc.close()
