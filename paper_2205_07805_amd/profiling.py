@@ -61,7 +61,7 @@ def family(name: str) -> str | None:
     s = short_name(name)
     if not s.startswith("igs::"):
         return None
-    for key in ("spmv_csr_kernel", "gemv_dense_kernel"):
+    for key in ("spmv_csr_kernel", "spmv_ell_kernel", "gemv_dense_kernel"):
         if key in s:
             return "spmv"
     for key, fam in (("reduce_kernel", "reduce"), ("update_kernel", "update"),
