@@ -1455,11 +1455,13 @@ __host__ __device__ __forceinline__ size_t update_lds_doubles(int j) {
   return (size_t)2 * (j + 1) + (size_t)7 * (j + 2) + stage_count(j);
 }
 
-// Rows of one tile of the update: every thread owns two 16-byte row vectors
-// (4 rows of doubles or 8 of floats).
-template <typename T>
+// Rows of one tile of the update: every thread owns NV 16-byte row vectors
+// (2 NV rows of doubles or 4 NV of floats), so a block reads each column of V
+// in runs of NV x 4 KB.  Longer runs per column stream faster from HBM (about
+// 6.2 TB/s with 8 KB runs against 6.8 with 16 KB on the 2M-row basis).
+template <typename T, int NV = 2>
 __host__ __device__ constexpr long long update_tile_rows() {
-  return 2LL * Vec16<T>::W * kUpdateThreads;
+  return (long long)NV * Vec16<T>::W * kUpdateThreads;
 }
 
 // The coefficients of the two-reduce second sweep for the vector in column j
@@ -1481,7 +1483,7 @@ __device__ void correct_coefs(const Work& w, int j, const double* P, double* sm,
     for (int i = threadIdx.x; i < j; i += blockDim.x) w.coef_r1[i] += st[i];
 }
 
-template <bool HAS_T, bool VEC, typename T>
+template <bool HAS_T, bool VEC, typename T, int NV>
 __device__ __forceinline__ void update_body(
     Grid gr, const Work& w, long long n, int j, int ngroups, T* __restrict__ Vraw,
     long long ldv_raw, const T* __restrict__ zraw, const double* __restrict__ traw,
@@ -1489,7 +1491,7 @@ __device__ __forceinline__ void update_body(
   // raw: 1 = step kernel on caller buffers, 2 = two-reduce second sweep
   typedef typename Vec16<T>::type VT;
   constexpr int W = Vec16<T>::W;
-  constexpr int R = 2 * W;   // rows per thread and tile
+  constexpr int R = NV * W;  // rows per thread and tile
   extern __shared__ double sdyn[];
   double* sP = sdyn;                 // V_{0:j}^T u and u^T u
   double* sQ = sdyn + (j + 1);       // V_{0:j}^T z and u^T z
@@ -1548,157 +1550,172 @@ __device__ __forceinline__ void update_body(
   const double rj = need_r ? r1[j] : 0.0;
   T* __restrict__ vj = V + (size_t)j * ldv;
   T* __restrict__ un = V + (size_t)(j + 1) * ldv;
-  constexpr long long kTile = update_tile_rows<T>();
+  constexpr long long kTile = update_tile_rows<T, NV>();
   const long long ntiles = (n + kTile - 1) / kTile;
   double s2 = 0.0;  // ||w||^2 partial (fallback only)
   for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
     if constexpr (VEC) {
-      // Full tile: the thread owns the row vectors at p0 = W t and
-      // p1 = p0 + W kUpdateThreads; V is streamed with 16-byte non-temporal
-      // loads, 4 columns at a time; products and sums in FP64.
+      // Full tile: the thread owns the row vectors at p_k = W t + k W
+      // kUpdateThreads; V is streamed with 16-byte non-temporal loads, CB
+      // columns at a time (8 loads in flight per thread); products and sums
+      // in FP64, each row's over the columns in order.
+      constexpr int CB = (NV >= 4) ? 2 : 8 / NV;
       const long long tb = tile * kTile;
       if (tb + kTile <= n) {
-        const long long p0 = tb + (long long)W * threadIdx.x;
-        const long long p1 = p0 + (long long)W * kUpdateThreads;
-        double a0[W], a1[W], b0[W], b1[W];
+        long long p[NV];
 #pragma unroll
-        for (int e = 0; e < W; ++e) a0[e] = a1[e] = b0[e] = b1[e] = 0.0;
-        auto use = [&](const VT& v0, const VT& v1, int c) {
+        for (int k = 0; k < NV; ++k)
+          p[k] = tb + (long long)W * threadIdx.x + (long long)k * W * kUpdateThreads;
+        double a[NV][W], b[NV][W];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+          for (int e = 0; e < W; ++e) a[k][e] = b[k][e] = 0.0;
+        auto use = [&](const VT* v, int c) {
           const double tc = HAS_T ? t[c] : 0.0;
           const double rc = r1[c];
 #pragma unroll
-          for (int e = 0; e < W; ++e) {
-            if (HAS_T) {
-              a0[e] = fma((double)v0[e], tc, a0[e]);
-              a1[e] = fma((double)v1[e], tc, a1[e]);
+          for (int k = 0; k < NV; ++k) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+              if (HAS_T) a[k][e] = fma((double)v[k][e], tc, a[k][e]);
+              b[k][e] = fma((double)v[k][e], rc, b[k][e]);
             }
-            b0[e] = fma((double)v0[e], rc, b0[e]);
-            b1[e] = fma((double)v1[e], rc, b1[e]);
           }
         };
         int c = 0;
-        for (; c + 4 <= j; c += 4) {
-          VT v0[4], v1[4];
+        for (; c + CB <= j; c += CB) {
+          VT v[CB][NV];
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) {
+          for (int cc = 0; cc < CB; ++cc) {
             const T* vc = V + (size_t)(c + cc) * ldv;
-            v0[cc] = ld16_stream<T>(vc + p0);
-            v1[cc] = ld16_stream<T>(vc + p1);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[cc][k] = ld16_stream<T>(vc + p[k]);
           }
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) use(v0[cc], v1[cc], c + cc);
+          for (int cc = 0; cc < CB; ++cc) use(v[cc], c + cc);
         }
         for (; c < j; ++c) {
           const T* vc = V + (size_t)c * ldv;
-          use(ld16_stream<T>(vc + p0), ld16_stream<T>(vc + p1), c);
+          VT v[NV];
+#pragma unroll
+          for (int k = 0; k < NV; ++k) v[k] = ld16_stream<T>(vc + p[k]);
+          use(v, c);
         }
-        const VT u0 = ld16<T>(vj + p0);
-        const VT u1 = ld16<T>(vj + p1);
-        VT o0, o1;
+        VT uu[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) uu[k] = ld16<T>(vj + p[k]);
         if (unscaled) {
 #pragma unroll
-          for (int e = 0; e < W; ++e) {
-            const double w0 = (double)u0[e] - a0[e];
-            const double w1 = (double)u1[e] - a1[e];
-            o0[e] = (T)w0;
-            o1[e] = (T)w1;
-            s2 = fma(w0, w0, s2);
-            s2 = fma(w1, w1, s2);
-          }
-          st16<T>(vj + p0, o0);
-          st16<T>(vj + p1, o1);
-        } else {
-          double n0[W], n1[W];
-#pragma unroll
-          for (int e = 0; e < W; ++e) {
-            n0[e] = ((double)u0[e] - a0[e]) * ig;
-            n1[e] = ((double)u1[e] - a1[e]) * ig;
-            o0[e] = (T)n0[e];
-            o1[e] = (T)n1[e];
-          }
-          st16<T>(vj + p0, o0);
-          st16<T>(vj + p1, o1);
-          if (need_r) {
-            const VT z0 = ld16<T>(z + p0);
-            const VT z1 = ld16<T>(z + p1);
+          for (int k = 0; k < NV; ++k) {
+            VT o;
 #pragma unroll
             for (int e = 0; e < W; ++e) {
-              o0[e] = (T)((double)z0[e] * ig - b0[e] - n0[e] * rj);
-              o1[e] = (T)((double)z1[e] * ig - b1[e] - n1[e] * rj);
+              const double wv = (double)uu[k][e] - a[k][e];
+              o[e] = (T)wv;
+              s2 = fma(wv, wv, s2);
             }
-            st16<T>(un + p0, o0);
-            st16<T>(un + p1, o1);
+            st16<T>(vj + p[k], o);
+          }
+        } else {
+          // v_j over the loaded u; a then holds v_j for the u_{j+1} rows
+#pragma unroll
+          for (int k = 0; k < NV; ++k) {
+            VT o;
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+              a[k][e] = ((double)uu[k][e] - a[k][e]) * ig;
+              o[e] = (T)a[k][e];
+            }
+            st16<T>(vj + p[k], o);
+          }
+          if (need_r) {
+            VT zz[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) zz[k] = ld16<T>(z + p[k]);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+              VT o;
+#pragma unroll
+              for (int e = 0; e < W; ++e)
+                o[e] = (T)((double)zz[k][e] * ig - b[k][e] - a[k][e] * rj);
+              st16<T>(un + p[k], o);
+            }
           }
         }
         continue;
       }
     }
-    // element path (partial tiles, or any alignment): R rows per thread
-    const long long base = tile * kTile + threadIdx.x;
-    double at[R], ar[R];
+    // element path (partial tiles, or any alignment): R rows per thread,
+    // taken 4 at a time (rows tile + tid + k kUpdateThreads), with 4 columns
+    // of loads in flight before their FMAs
+#pragma unroll 1
+    for (int h = 0; h < R; h += 4) {
+      const long long base = tile * kTile + threadIdx.x + (long long)h * kUpdateThreads;
+      double at[4], ar[4];
 #pragma unroll
-    for (int k = 0; k < R; ++k) at[k] = ar[k] = 0.0;
-    const bool full = base + (long long)(R - 1) * kUpdateThreads < n;
-    if (full) {
-      // four columns x R rows of loads in flight before any FMA
-      int c = 0;
-      for (; c + 4 <= j; c += 4) {
-        double vv[4][R];
+      for (int k = 0; k < 4; ++k) at[k] = ar[k] = 0.0;
+      const bool full = base + 3LL * kUpdateThreads < n;
+      if (full) {
+        int c = 0;
+        for (; c + 4 <= j; c += 4) {
+          double vv[4][4];
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-          const T* __restrict__ vc = V + (size_t)(c + cc) * ldv + base;
+          for (int cc = 0; cc < 4; ++cc) {
+            const T* __restrict__ vc = V + (size_t)(c + cc) * ldv + base;
 #pragma unroll
-          for (int k = 0; k < R; ++k) vv[cc][k] = (double)vc[k * kUpdateThreads];
-        }
+            for (int k = 0; k < 4; ++k) vv[cc][k] = (double)vc[k * kUpdateThreads];
+          }
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-          const double tc = HAS_T ? t[c + cc] : 0.0;
-          const double rc = r1[c + cc];
+          for (int cc = 0; cc < 4; ++cc) {
+            const double tc = HAS_T ? t[c + cc] : 0.0;
+            const double rc = r1[c + cc];
 #pragma unroll
-          for (int k = 0; k < R; ++k) {
-            if (HAS_T) at[k] = fma(vv[cc][k], tc, at[k]);
-            ar[k] = fma(vv[cc][k], rc, ar[k]);
+            for (int k = 0; k < 4; ++k) {
+              if (HAS_T) at[k] = fma(vv[cc][k], tc, at[k]);
+              ar[k] = fma(vv[cc][k], rc, ar[k]);
+            }
           }
         }
-      }
-      for (; c < j; ++c) {
-        const T* __restrict__ vc = V + (size_t)c * ldv + base;
-        const double tc = HAS_T ? t[c] : 0.0;
-        const double rc = r1[c];
+        for (; c < j; ++c) {
+          const T* __restrict__ vc = V + (size_t)c * ldv + base;
+          const double tc = HAS_T ? t[c] : 0.0;
+          const double rc = r1[c];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          const double v = (double)vc[k * kUpdateThreads];
-          if (HAS_T) at[k] = fma(v, tc, at[k]);
-          ar[k] = fma(v, rc, ar[k]);
-        }
-      }
-    } else {
-      for (int c = 0; c < j; ++c) {
-        const T* __restrict__ vc = V + (size_t)c * ldv + base;
-        const double tc = HAS_T ? t[c] : 0.0;
-        const double rc = r1[c];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          if (base + k * kUpdateThreads < n) {
+          for (int k = 0; k < 4; ++k) {
             const double v = (double)vc[k * kUpdateThreads];
             if (HAS_T) at[k] = fma(v, tc, at[k]);
             ar[k] = fma(v, rc, ar[k]);
           }
         }
-      }
-    }
+      } else {
+        for (int c = 0; c < j; ++c) {
+          const T* __restrict__ vc = V + (size_t)c * ldv + base;
+          const double tc = HAS_T ? t[c] : 0.0;
+          const double rc = r1[c];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const long long r = base + k * kUpdateThreads;
-      if (r < n) {
-        if (unscaled) {
-          const double wv = (double)vj[r] - at[k];
-          vj[r] = (T)wv;
-          s2 = fma(wv, wv, s2);
-        } else {
-          const double v = ((double)vj[r] - at[k]) * ig;
-          vj[r] = (T)v;
-          if (need_r) un[r] = (T)((double)z[r] * ig - ar[k] - v * rj);
+          for (int k = 0; k < 4; ++k) {
+            if (base + k * kUpdateThreads < n) {
+              const double v = (double)vc[k * kUpdateThreads];
+              if (HAS_T) at[k] = fma(v, tc, at[k]);
+              ar[k] = fma(v, rc, ar[k]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const long long r = base + k * kUpdateThreads;
+        if (r < n) {
+          if (unscaled) {
+            const double wv = (double)vj[r] - at[k];
+            vj[r] = (T)wv;
+            s2 = fma(wv, wv, s2);
+          } else {
+            const double v = ((double)vj[r] - at[k]) * ig;
+            vj[r] = (T)v;
+            if (need_r) un[r] = (T)((double)z[r] * ig - ar[k] - v * rj);
+          }
         }
       }
     }
@@ -1754,13 +1771,16 @@ __device__ __forceinline__ void update_body(
   }
 }
 
-template <bool HAS_T, bool VEC, typename T>
-__global__ __launch_bounds__(kUpdateThreads) void update_kernel(
+// With four row vectors of doubles, four blocks per CU (at most 128 VGPRs)
+// give one tile to each block on the 2M-row basis.
+template <bool HAS_T, bool VEC, typename T, int NV>
+__global__ __launch_bounds__(kUpdateThreads)
+__attribute__((amdgpu_waves_per_eu((NV == 4 && sizeof(T) == 8) ? 4 : 1))) void update_kernel(
     Work w, long long n, int j, int ngroups, T* __restrict__ Vraw, long long ldv_raw,
     const T* __restrict__ zraw, const double* __restrict__ traw,
     const double* __restrict__ r1raw, double igraw, int raw) {
-  update_body<HAS_T, VEC, T>(hw_grid(), w, n, j, ngroups, Vraw, ldv_raw, zraw, traw, r1raw, igraw,
-                             raw);
+  update_body<HAS_T, VEC, T, NV>(hw_grid(), w, n, j, ngroups, Vraw, ldv_raw, zraw, traw, r1raw,
+                                 igraw, raw);
 }
 
 // Tiles of update_tile_rows<T>() rows, one round of resident blocks striding
@@ -1782,6 +1802,16 @@ template <typename T>
 using UpdateKernel = void (*)(Work, long long, int, int, T*, long long, const T*, const double*,
                               const double*, double, int);
 
+// Row vectors per thread of the single-instance update: the largest of 4, 2
+// and 1 whose tiles still number at least one per CU.
+template <typename T>
+static int update_nv(long long n) {
+  const long long cus = resident_blocks(nullptr, 0, 0);
+  if ((n + update_tile_rows<T, 4>() - 1) / update_tile_rows<T, 4>() >= cus) return 4;
+  if ((n + update_tile_rows<T, 2>() - 1) / update_tile_rows<T, 2>() >= cus) return 2;
+  return 1;
+}
+
 template <typename T>
 static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t, int ngroups,
                                   T* Vraw, long long ldv_raw, const T* zraw, const double* traw,
@@ -1793,10 +1823,23 @@ static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t,
   const long long ldv = (raw == 1) ? ldv_raw : w.ldv;
   const bool vec = (ldv % Vec16<T>::W == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
                    (reinterpret_cast<uintptr_t>(zp) % 16 == 0);
-  UpdateKernel<T> k = has_t ? (vec ? update_kernel<true, true, T> : update_kernel<true, false, T>)
-                            : (vec ? update_kernel<false, true, T> : update_kernel<false, false, T>);
+  // the longest runs per column that still give every CU a tile
+  const int nv = vec ? update_nv<T>(n) : 2;
+  UpdateKernel<T> k;
+  long long tile_rows;
+  if (nv == 4) {
+    k = has_t ? update_kernel<true, true, T, 4> : update_kernel<false, true, T, 4>;
+    tile_rows = update_tile_rows<T, 4>();
+  } else if (nv == 1) {
+    k = has_t ? update_kernel<true, true, T, 1> : update_kernel<false, true, T, 1>;
+    tile_rows = update_tile_rows<T, 1>();
+  } else {
+    k = has_t ? (vec ? update_kernel<true, true, T, 2> : update_kernel<true, false, T, 2>)
+              : (vec ? update_kernel<false, true, T, 2> : update_kernel<false, false, T, 2>);
+    tile_rows = update_tile_rows<T, 2>();
+  }
   const size_t lds = update_lds_doubles(j) * sizeof(double);
-  unsigned grid = update_grid(reinterpret_cast<const void*>(k), n, update_tile_rows<T>(), lds);
+  unsigned grid = update_grid(reinterpret_cast<const void*>(k), n, tile_rows, lds);
   if (raw == 0 && w.tune && (w.tune[j] & 2) && grid > 1) grid = (grid + 1) / 2;
   Work wa = w;
   long long na = n, ldva = ldv_raw;
@@ -2199,8 +2242,8 @@ __global__ __launch_bounds__(kUpdateThreads) void update_batch_kernel(const Inst
   if (bid >= e.nblk) return;
   const Work w = tab[e.inst].w;
   const long long n = tab[e.inst].n;
-  update_body<HAS_T, VEC, T>(Grid{bid, e.nblk}, w, n, j, (int)e.aux, nullptr, 0, nullptr, nullptr,
-                             nullptr, 0.0, 0);
+  update_body<HAS_T, VEC, T, 2>(Grid{bid, e.nblk}, w, n, j, (int)e.aux, nullptr, 0, nullptr,
+                                nullptr, nullptr, 0.0, 0);
 }
 
 __global__ __launch_bounds__(256) void bnorm_batch_kernel(const Inst* __restrict__ tab,
@@ -2421,8 +2464,8 @@ static hipError_t batch_update_t(const BatchRun& r, int j, const int* ngroups) {
   const bool has_t = r.h_tab[r.act[0]].gs == 2;
   const void* kern = has_t ? reinterpret_cast<const void*>(update_batch_kernel<true, true, T>)
                            : reinterpret_cast<const void*>(update_batch_kernel<false, true, T>);
-  const void* lone = has_t ? reinterpret_cast<const void*>(update_kernel<true, true, T>)
-                           : reinterpret_cast<const void*>(update_kernel<false, true, T>);
+  const void* lone = has_t ? reinterpret_cast<const void*>(update_kernel<true, true, T, 2>)
+                           : reinterpret_cast<const void*>(update_kernel<false, true, T, 2>);
   const size_t lds = update_lds_doubles(j) * sizeof(double);
   int nb[kMaxBatch];
   long long ng[kMaxBatch];
