@@ -37,7 +37,9 @@ def _random_csr(n, avg, seed, empty_rows=()):
 
 CSR_CASES = {
     "convdiff3d_17": lambda: W.convdiff3d(17, 50.0),
+    "convdiff3d_16": lambda: W.convdiff3d(16, 50.0),
     "convdiff2d_31": lambda: W.convdiff2d(31, 10.0),
+    "convdiff2d_32": lambda: W.convdiff2d(32, 10.0),
     "random_short_rows_empty": lambda: _random_csr(3001, 3.0, 1, empty_rows=(0, 17, 3000)),
     "random_two_lanes": lambda: _random_csr(2049, 1.6, 5, empty_rows=(5,)),
     "diagonal_one_lane": lambda: W.csr_from_dense(np.diag(np.arange(1.0, 40.0))),
@@ -141,9 +143,12 @@ def test_reduce_matches_oracle(torch, n, j, pad):
     assert np.array_equal(P2, P)
 
 
+# 300,001 and 600,001 rows take two and four row vectors per thread (the
+# tiles then number at least one per CU), with a partial last tile; with
+# pad 3 the leading dimension is even and the vector path runs
 @pytest.mark.parametrize("pad", [3, 64], ids=["ld_odd", "ld_even"])
 @pytest.mark.parametrize("j", [0, 1, 7, 33, 60])
-@pytest.mark.parametrize("n", [100_003, 1_025, 4_096])
+@pytest.mark.parametrize("n", [100_003, 1_025, 4_096, 300_001, 600_001])
 def test_update_matches_oracle(torch, n, j, pad):
     from paper_2205_07805_amd import igs
     print(f"update n={n} j={j} ldv=n+{pad}", flush=True)
@@ -168,7 +173,8 @@ def test_update_matches_oracle(torch, n, j, pad):
     assert np.all(out[:, n:] == 0.0)
 
 
-@pytest.mark.parametrize("case", ["convdiff2d_31", "convdiff3d_17"])
+# odd n: one row per thread; even n: two
+@pytest.mark.parametrize("case", ["convdiff2d_31", "convdiff3d_17", "convdiff2d_32", "convdiff3d_16"])
 def test_ell_form_is_bit_identical_to_csr(torch, case):
     """Short-row operators also keep a column-major ELL form; its product
     must equal the CSR kernel's bit for bit.  A copy of the matrix with four
