@@ -85,6 +85,34 @@ def test_mixed_convdiff3d_37_ragged(torch):
     assert xerr <= 1e3 * tol
 
 
+def test_convdiff3d_103_four_row_vectors_ragged(torch):
+    """n = 103^3 = 1,092,727 rows: the update pass takes four row vectors per
+    thread in FP64 (2,048-row tiles) and in FP32 (4,096-row tiles), each with
+    a partial last tile, and the operator apply one row per thread (odd n).
+    Both solves reach the tolerance, their first-cycle Hessenberg columns
+    match the FP64 oracle's (FP64 to 1e-11, FP32 cycles to 1e-5), and the
+    two solutions agree to what the tolerance implies."""
+    a = W.convdiff3d(103, 50.0)
+    b = W.rhs_normal(a.n, 0)
+    tol = 1e-12
+    op = O.as_operator(a)
+    ref = O.gmres(a, b, restart=40, tol=tol, variant="igs1r", max_cycles=1).first_cycle
+    print(f"convdiff3d_103 n={a.n}", flush=True)
+    xs = {}
+    for fp32 in (0, 1):
+        x, rc, info, H = solve(a, b, 40, tol, 2, inner_fp32=fp32, maxit=6000)
+        relres = np.linalg.norm(b - op.matvec(x)) / np.linalg.norm(b)
+        herr = h_rel_err(H, ref.H, 10)
+        print(f"  fp32={fp32}: rc {rc} iters {info['iters']} relres {relres:.2e} "
+              f"H cols 0..9 rel err {herr:.2e}", flush=True)
+        assert rc == 0 and info["converged"] == 1 and relres <= tol
+        assert herr <= (1e-5 if fp32 else 1e-11)
+        xs[fp32] = x
+    d = np.abs(xs[1] - xs[0]).max() / np.abs(xs[0]).max()
+    print(f"  max|x32 - x64|/max|x64| {d:.2e}", flush=True)
+    assert d <= 1e3 * tol
+
+
 def test_mixed_convdiff3d_96_backward_error(torch):
     """The 96^3 system (n = 884,736): GMRES(40) with FP32 cycles reaches
     backward error <= 1e-14 like the FP64 solve."""
