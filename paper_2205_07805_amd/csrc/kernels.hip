@@ -207,11 +207,11 @@ __device__ void sum_rows(const double* src, int pstride, int cnt, int nv, double
 // that its one wait publishes all of them).
 //
 // First level (group_reduce_last): the blocks are split into up to 8 groups
-// by bid % 8 -- the blocks of one group then run on one XCD under the
-// hardware's round-robin dispatch, so a group's partials and its counter stay
-// in one L2 (the result does not depend on where blocks run) -- and the last
-// block of a group to arrive sums that group in a fixed order into gpart[g]
-// and resets the group's counter.  Returns true in that block, with out[v]
+// by bid % 8 (under the hardware's round-robin dispatch the blocks of one
+// group run on one XCD; the result does not depend on where blocks run), so
+// eight counters share the arrivals, and the last block of a group to arrive
+// sums that group in a fixed order into gpart[g] and resets the group's
+// counter.  Returns true in that block, with out[v]
 // (shared memory) holding the group's totals.  scratch: shared memory of
 // max(blockDim.x, nv) doubles, disjoint from out.  publish_all: the last
 // block also reads other data that blocks wrote with plain stores in this
