@@ -106,12 +106,12 @@ typedef struct igs_opts {
                              instances share a launch).  1: the grid a lone
                              solve launches (then every member is
                              bit-identical to igs_solve_opts, except the
-                             explicit norm of a lagged-norm fallback when the
-                             lone update takes longer tiles, from 524,288
-                             FP64 rows on); <= 0: 4096                       */
-  int batch_update_tiles; /* batches: at least this many tiles (1,024 rows of
-                             FP64, 2,048 of FP32) per block of the update.
-                             1: one tile per block; <= 0: 4                  */
+                             explicit norm of a lagged-norm fallback, whose
+                             per-thread partial sums follow the update's
+                             tiles); <= 0: 4096                              */
+  int batch_update_tiles; /* batches: at least this many tiles (2,048 rows of
+                             FP64, 4,096 of FP32) per block of the update.
+                             1: one tile per block; <= 0: 2                  */
   int cycle_graph;      /* 1: record the launches of a restart cycle in a HIP
                            graph once and replay it for every cycle (one
                            launch instead of 3(m+1)+4); the graph is kept in

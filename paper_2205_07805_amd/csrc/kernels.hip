@@ -2294,16 +2294,21 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_batch_kernel(const Inst
                               nullptr);
 }
 
+// Row vectors per thread of the batched update (tiles of 2,048 FP64 rows):
+// 16 KB runs per column, as the single-instance update takes on large n.
+constexpr int kBatchNV = 4;
+
 template <bool HAS_T, bool VEC, typename T>
-__global__ __launch_bounds__(kUpdateThreads) void update_batch_kernel(const Inst* __restrict__ tab,
-                                                                      BatchMap map, int j) {
+__global__ __launch_bounds__(kUpdateThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1))) void update_batch_kernel(
+    const Inst* __restrict__ tab, BatchMap map, int j) {
   const MapEntry e = map_find(map);
   const int bid = (int)blockIdx.x - e.start;
   if (bid >= e.nblk) return;
   const Work w = tab[e.inst].w;
   const long long n = tab[e.inst].n;
-  update_body<HAS_T, VEC, T, 2>(Grid{bid, e.nblk}, w, n, j, (int)e.aux, nullptr, 0, nullptr,
-                                nullptr, nullptr, 0.0, 0);
+  update_body<HAS_T, VEC, T, kBatchNV>(Grid{bid, e.nblk}, w, n, j, (int)e.aux, nullptr, 0,
+                                       nullptr, nullptr, nullptr, 0.0, 0);
 }
 
 __global__ __launch_bounds__(256) void bnorm_batch_kernel(const Inst* __restrict__ tab,
@@ -2524,16 +2529,17 @@ static hipError_t batch_update_t(const BatchRun& r, int j, const int* ngroups) {
   const bool has_t = r.h_tab[r.act[0]].gs == 2;
   const void* kern = has_t ? reinterpret_cast<const void*>(update_batch_kernel<true, true, T>)
                            : reinterpret_cast<const void*>(update_batch_kernel<false, true, T>);
-  const void* lone = has_t ? reinterpret_cast<const void*>(update_kernel<true, true, T, 2>)
-                           : reinterpret_cast<const void*>(update_kernel<false, true, T, 2>);
+  const void* lone = has_t ? reinterpret_cast<const void*>(update_kernel<true, true, T, kBatchNV>)
+                           : reinterpret_cast<const void*>(update_kernel<false, true, T, kBatchNV>);
   const size_t lds = update_lds_doubles(j) * sizeof(double);
   int nb[kMaxBatch];
   long long ng[kMaxBatch];
   const long long tmin = r.update_tiles > 1 ? r.update_tiles : 1;
   for (int k = 0; k < r.count; ++k) {
     const long long n = r.h_tab[r.act[k]].n;
-    const long long g = update_grid(lone, n, update_tile_rows<T>(), lds);
-    const long long tiles = (n + update_tile_rows<T>() - 1) / update_tile_rows<T>();
+    constexpr long long kRows = update_tile_rows<T, kBatchNV>();
+    const long long g = update_grid(lone, n, kRows, lds);
+    const long long tiles = (n + kRows - 1) / kRows;
     const long long want = (tiles + tmin - 1) / tmin;
     nb[k] = (int)(want < g ? want : g);
     ng[k] = ngroups[k];

@@ -1349,7 +1349,7 @@ struct BatchParams {
   int gs = 2;
   double tol = 0.0, tau = 1e-4, cycle_rtol = 0.0;
   int final_v = 0, fp32 = 0, max_cycles = 0;
-  int reduce_rows = 4096, update_tiles = 4;
+  int reduce_rows = 4096, update_tiles = 2;
 };
 
 void batch_free(Batch& B) {
@@ -1589,7 +1589,7 @@ int batch_params(const igs_opts& o, int gs_iters, double tol, BatchParams* p, st
   p->cycle_rtol = p->fp32 ? (o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5) : 0.0;
   p->max_cycles = o.max_cycles;
   p->reduce_rows = o.batch_reduce_rows > 0 ? o.batch_reduce_rows : 4096;
-  p->update_tiles = o.batch_update_tiles > 0 ? o.batch_update_tiles : 4;
+  p->update_tiles = o.batch_update_tiles > 0 ? o.batch_update_tiles : 2;
   return IGS_OK;
 }
 
