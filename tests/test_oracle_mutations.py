@@ -207,3 +207,60 @@ def test_rounding_level_terms(monkeypatch, name):
     for col in range(m):
         assert np.linalg.norm(mut.H[: col + 2, col] - ref.H[: col + 2, col]) <= \
             1e-12 * np.linalg.norm(ref.H[: col + 2, col])
+
+
+# ---- diagnostics: planted mistakes caught by their pins ---------------------
+
+def _run_pins(pins):
+    failed = 0
+    for pin, args in pins:
+        try:
+            pin(*args)
+        except AssertionError:
+            failed += 1
+    return failed
+
+
+BACKWARD_ERROR_MUTATIONS = {
+    "denominator without ||b||":
+        lambda op, b, x, an: np.linalg.norm(b - op.matvec(x)) / (an * np.linalg.norm(x)),
+    "denominator without ||A|| ||x||":
+        lambda op, b, x, an: np.linalg.norm(b - op.matvec(x)) / np.linalg.norm(b),
+    "||A|| dropped from the denominator":
+        lambda op, b, x, an: np.linalg.norm(b - op.matvec(x)) / (np.linalg.norm(b) + np.linalg.norm(x)),
+    "squared norms":
+        lambda op, b, x, an: float((b - op.matvec(x)) @ (b - op.matvec(x)))
+        / (float(b @ b) + an * an * float(x @ x)),
+    "residual with the wrong sign of A x":
+        lambda op, b, x, an: np.linalg.norm(b + op.matvec(x)) / (np.linalg.norm(b) + an * np.linalg.norm(x)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BACKWARD_ERROR_MUTATIONS))
+def test_backward_error_mutations_caught(monkeypatch, name):
+    import test_oracle_primitives as P
+    monkeypatch.setattr(D, "backward_error", BACKWARD_ERROR_MUTATIONS[name])
+    pins = [(P.test_backward_error_rigal_gaches_construction, (k,)) for k in range(3)]
+    pins.append((P.test_backward_error_hand_computed_2x2, ()))
+    assert _run_pins(pins) >= 2, name
+
+
+GS_RADIUS_MUTATIONS = {
+    "L not transposed": lambda L: float(np.max(np.abs(np.linalg.eigvals(
+        -np.linalg.solve(np.eye(L.shape[0]) + L, L))))) if L.shape[0] else 0.0,
+    "Jacobi matrix": lambda L: float(np.max(np.abs(np.linalg.eigvals(-(L + L.T))))) if L.shape[0] else 0.0,
+    "wrong sign inside (I - L)": lambda L: float(np.max(np.abs(np.linalg.eigvals(
+        -np.linalg.solve(np.eye(L.shape[0]) - L, L.T))))) if L.shape[0] else 0.0,
+    "no inverse": lambda L: float(np.max(np.abs(np.linalg.eigvals(-L.T)))) if L.shape[0] else 0.0,
+}
+
+
+@pytest.mark.parametrize("name", sorted(GS_RADIUS_MUTATIONS))
+def test_gs_spectral_radius_mutations_caught(monkeypatch, name):
+    import test_oracle_primitives as P
+    monkeypatch.setattr(D, "gs_spectral_radius", GS_RADIUS_MUTATIONS[name])
+    pins = [(P.test_gs_spectral_radius_closed_form_2x2, ()),
+            (P.test_gs_spectral_radius_young_tridiagonal, ()),
+            (P.test_gs_spectral_radius_small_for_near_orthogonal_basis, ()),
+            (P.test_gs_spectral_radius_is_the_sweep_contraction_rate, ())]
+    assert _run_pins(pins) >= 1, name
