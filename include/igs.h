@@ -236,8 +236,11 @@ typedef struct igs_request {
  *     the last completion (may be NULL).
  * The memory a request holds is 12 nnz + 4 (n+1) + 8 n (m'+5) + 32 (m'+2)^2
  * bytes with m' = min(restart, n), plus 4 nnz + 4 n (m'+2) with inner_fp32
- * (the FP32 basis and values).  The slots themselves hold `slots` times
- * the footprint of the largest request, allocated once at the start.
+ * (the FP32 basis and values).  Each slot holds the footprint of the
+ * largest request of the trace (n and nnz taken at their maxima), allocated
+ * once at the start; the loop runs min(slots, mem_cap / that footprint)
+ * slots, at least one, so that the slots' device memory stays within
+ * mem_cap whenever one slot fits it.
  * Returns IGS_OK when the trace was served: each request's rc tells its own
  * outcome (IGS_EINVAL for a malformed CSR, IGS_ENOCONV, ...), and the other
  * requests run regardless.  IGS_EINVAL for bad arguments or a request larger
@@ -287,7 +290,9 @@ int igs_solve_batch(igs_ctx *const *ctxs, const double *const *b, double *const 
  * requests leave (x copied back) and the oldest arrived requests join while a
  * member is free and the memory cap allows.  Requests, memory accounting,
  * outputs and return codes are those of igs_serve; each x is bit-identical to
- * a lone solve.  two_reduce is not supported (IGS_ENOTIMPL).
+ * a lone solve.  The batch is limited to the members the cap holds at the
+ * largest footprint, as igs_serve limits its slots.  two_reduce is not
+ * supported (IGS_ENOTIMPL).
  */
 int igs_serve_batched(igs_request *reqs, int nreq, int batch, int64_t mem_cap, int restart,
                       double tol, int gs_iters, const igs_opts *opts, double *wall_seconds);

@@ -1031,10 +1031,13 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
   if (s_flag) {
     // Cancellation in u^T u - p^T p: every block forms w = u - V t and its
     // explicit norm; the publisher leaves the column without its subdiagonal.
-    if (pub) {
+    // Wave 0 alone stores it: the last block of the explicit-norm reduction
+    // in this launch reads it, and the release fence before wave 0's arrival
+    // at that reduction orders wave 0's own stores only.
+    if (pub && wave == 0) {
       double* hc = w.H + hess_col(j - 1);
-      for (int i = tid; i < j; i += blockDim.x) hc[i] = shc[i];
-      if (tid == 0) {
+      for (int i = lane; i < j; i += kWave) hc[i] = shc[i];
+      if (lane == 0) {
         ctl->mode = kUpdFallback;
         ctl->mode_iter = j;
       }

@@ -26,7 +26,10 @@ using igs::Work;
 
 namespace {
 
-thread_local std::string g_create_error;
+// Message of the last failing call that has no context (igs_create*, the
+// serving and no-allocation entry points): a fixed buffer, so that setting it
+// allocates nothing.
+thread_local char g_create_error[512];
 
 struct EventPair {
   hipEvent_t a, b;
@@ -134,7 +137,7 @@ int set_err(igs_ctx* c, int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (c) c->err = buf; else g_create_error = buf;
+  if (c) c->err = buf; else snprintf(g_create_error, sizeof g_create_error, "%s", buf);
   return code;
 }
 
@@ -396,7 +399,7 @@ int common_create(igs_ctx** out, void* hip_stream, igs_ctx** made) {
 }
 
 int fail_create(igs_ctx* c, int code) {
-  g_create_error = c->err;
+  snprintf(g_create_error, sizeof g_create_error, "%s", c->err.c_str());
   igs_destroy(c);
   return code;
 }
@@ -560,7 +563,7 @@ extern "C" int igs_destroy(igs_ctx* c) {
 }
 
 extern "C" const char* igs_last_error(const igs_ctx* c) {
-  return c ? c->err.c_str() : g_create_error.c_str();
+  return c ? c->err.c_str() : g_create_error;
 }
 
 extern "C" int igs_solve(igs_ctx* c, const double* b, double* x, int restart, double tol,
@@ -1211,9 +1214,14 @@ extern "C" int igs_serve(igs_request* reqs, int nreq, int slots, int64_t mem_cap
       return set_err(nullptr, IGS_EINVAL, "request %d needs %lld bytes, more than the cap", i,
                      need[i]);
   }
+  // Each slot holds the footprint of the largest request for the whole run:
+  // run no more slots than the cap holds (at least one), so that the device
+  // memory of the slots stays within it.
+  const long long slot_bytes = request_bytes(n_cap, nnz_cap, restart, o.inner_fp32 != 0);
+  slots = (int)std::max<long long>(1, std::min<long long>(slots, mem_cap / slot_bytes));
   std::vector<Slot> sl(slots);
   for (int k = 0; k < slots; ++k) {
-    const int rc = slot_create(sl[k], n_cap, nnz_cap, restart);
+    const int rc = slot_create(sl[k], n_cap, nnz_cap, restart, nullptr, o.inner_fp32 != 0);
     if (rc != IGS_OK) {
       for (Slot& x : sl) slot_destroy(x);
       return rc;
@@ -1690,6 +1698,9 @@ extern "C" int igs_serve_batched(igs_request* reqs, int nreq, int batch, int64_t
       return set_err(nullptr, IGS_EINVAL, "request %d needs %lld bytes, more than the cap", i,
                      need[i]);
   }
+  // as igs_serve: no more members than the cap holds at the largest footprint
+  const long long slot_bytes = request_bytes(n_cap, nnz_cap, restart, p.fp32 != 0);
+  batch = (int)std::max<long long>(1, std::min<long long>(batch, mem_cap / slot_bytes));
   hipStream_t stream = nullptr;
   if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
     return set_err(nullptr, IGS_EDEVICE, "cannot create a stream");

@@ -269,3 +269,4 @@ def igs_tune(ctx, restart, gs_iters=2) -> dict:
 
 def igs_tune_reset(ctx) -> None:
     _check("igs_tune_reset", load_library().igs_tune_reset(ctx), ctx)
+

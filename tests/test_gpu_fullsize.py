@@ -7,7 +7,10 @@ The oracle's step functions are vectorised, so every output is compared,
 not a sample: the operator apply, the fused reduction at j = 30 and 60 (with
 and without z), and the update at j = 59.  The whole solve is checked on the
 first cycle's Hessenberg columns 0..9 against the oracle's first cycle, and
-on its true relative residual and backward error.
+on its true relative residual and backward error; with one and with two
+sweeps it is run to convergence beside the oracle's solve (about half a
+minute of host time each): the iteration count within +-2, the first-cycle
+columns, and x.
 """
 import numpy as np
 import pytest
@@ -120,3 +123,43 @@ def test_fullsize_solve(torch, system):
     for c in range(10):
         hc, hr = H[: c + 2, c], ref.H[: c + 2, c]
         assert np.linalg.norm(hc - hr) <= 1e-11 * np.linalg.norm(hr), c
+
+
+@pytest.mark.parametrize("gs", [2, 1])
+def test_fullsize_solve_to_convergence_matches_oracle(torch, system, gs):
+    """Algorithm 4.2 (two sweeps) and Algorithm 4.1 stopped after its first
+    sweep (one sweep), GMRES(60) to tol 1e-10 at 128^3, against the oracle's
+    solve of the same variant.  x: both solutions have relative residual
+    <= tol, so ||A (x - x_oracle)|| <= 2 tol ||b|| whatever the rounding; the
+    two solves follow the same iterates up to rounding, so x also agrees to
+    1e-6 relative (far inside kappa(A) * 2 tol)."""
+    from paper_2205_07805_amd import Solver
+    a, b = system
+    tol = 1e-10
+    print(f"full-size solve to convergence gs={gs} n={a.n}", flush=True)
+    s = Solver(a)
+    try:
+        x, rc, info = s.solve(b, restart=60, tol=tol, gs_iters=gs)
+        H = s.first_cycle_H()
+    finally:
+        s.close()
+    xh = x.cpu().numpy()
+    v, g = ("igs1r", 2) if gs == 2 else ("igs2r", 1)
+    ref = O.gmres(a, b, restart=60, tol=tol, variant=v, gs_iters=g)
+    op = O.as_operator(a)
+    bn = np.linalg.norm(b)
+    dres = np.linalg.norm(op.matvec(xh - ref.x)) / bn
+    dx = np.linalg.norm(xh - ref.x) / np.linalg.norm(ref.x)
+    print(f"  gpu iters {info['iters']} oracle iters {ref.iters}; "
+          f"||A dx||/||b|| {dres:.2e}; ||dx||/||x|| {dx:.2e}", flush=True)
+    assert rc == 0 and info["converged"] == 1 and ref.converged
+    assert abs(info["iters"] - ref.iters) <= 2, (info["iters"], ref.iters)
+    assert np.linalg.norm(b - op.matvec(xh)) <= tol * bn
+    assert dres <= 2 * tol
+    assert dx <= 1e-6
+    assert info["first_cycle_J"] == ref.first_cycle.J == 60
+    for c in range(10):
+        hc, hr = H[: c + 2, c], ref.first_cycle.H[: c + 2, c]
+        nrm = np.linalg.norm(hr)
+        assert np.linalg.norm(hc - hr) <= 1e-11 * nrm, c
+        assert np.all(np.abs(hc - hr) <= 1e-11 * np.maximum(np.abs(hr), 1e-3 * nrm)), c

@@ -131,6 +131,19 @@ def test_mixed_convdiff3d_96_backward_error(torch):
     x64, x32 = out[0][0], out[1][0]
     print(f"  max|x32 - x64|/max|x64| {np.abs(x32 - x64).max() / np.abs(x64).max():.2e}", flush=True)
     assert out[1][1] <= 1.5 * out[0][1] + 80
+    # each result against the FP64 oracle's solve of the same system: every
+    # solution has relative residual <= tol, so ||A (x - x_oracle)|| <= 2 tol ||b||
+    ref = O.gmres(a, b, restart=40, tol=tol, variant="igs1r", maxit=4000)
+    assert ref.converged
+    bn = np.linalg.norm(b)
+    for fp32 in (0, 1):
+        x = out[fp32][0]
+        dres = np.linalg.norm(op.matvec(x - ref.x)) / bn
+        dmax = np.abs(x - ref.x).max() / np.abs(ref.x).max()
+        print(f"  fp32={fp32} against the FP64 oracle (iters {ref.iters}): "
+              f"max|x - x_oracle|/max|x_oracle| {dmax:.2e}, ||A dx||/||b|| {dres:.2e}", flush=True)
+        assert dres <= 2 * tol
+        assert dmax <= 1e-9
 
 
 def test_mixed_rejects_dense_and_first_basis(torch):

@@ -132,6 +132,55 @@ def test_lagnorm_guard_forced_matches_oracle(torch):
     np.testing.assert_allclose(x, ref.x, atol=1e-10)
 
 
+@pytest.mark.parametrize("fp32", [0, 1], ids=["fp64", "fp32_cycles"])
+def test_lagnorm_guard_forced_many_update_blocks(torch, fp32):
+    """The forced fallback on a system whose update kernel has many blocks
+    (37^3 = 50,653 rows: 99 update blocks in FP64, 50 with FP32 cycles, 8
+    groups), so the explicit norm is a real grid reduction and its last block
+    reads the column that block 0 stored in the same launch.  Every cycle
+    ends at its first column; six cycles against the oracle's six."""
+    a = W.convdiff3d(37, 50.0)
+    b = W.rhs_normal(a.n, 0)
+    print(f"lagnorm guard forced tau=2 n={a.n} fp32={fp32}", flush=True)
+    x, rc, info, H, _ = gpu(a, b, 30, 1e-12, 2, lagnorm_tau=2.0, max_cycles=6, inner_fp32=fp32)
+    ref = O.gmres(a, b, restart=30, tol=1e-12, variant="igs1r", lagnorm_tau=2.0, max_cycles=6)
+    assert rc == 1 and info["converged"] == 0                 # ENOCONV after six cycles
+    assert info["iters"] == ref.iters == 6
+    assert info["lagnorm_fallbacks"] == ref.lagnorm_fallbacks == 6
+    assert info["first_cycle_J"] == ref.first_cycle.J == 1
+    assert info["last_cycle_status"] == "lagnorm"
+    # column 0 of the first cycle: H[0,0] from the reduction, H[1,0] the explicit norm
+    htol = 1e-6 if fp32 else 1e-11
+    assert np.linalg.norm(H[:2, 0] - ref.first_cycle.H[:2, 0]) <= htol * np.linalg.norm(ref.first_cycle.H[:2, 0])
+    xtol = 1e-5 if fp32 else 1e-10
+    assert np.abs(x - ref.x).max() <= xtol * np.abs(ref.x).max()
+
+
+def test_nonfinite_mid_solve_returns_enumeric(torch):
+    """Finite values at create time, but the second product overflows
+    (|A| ~ 1e200): the reduction of iteration 1 is not finite, the solve stops
+    with IGS_ENUMERIC and x keeps x0."""
+    from paper_2205_07805_amd import Solver, igs
+    a = W.convdiff2d(8, 1.0)
+    big = W.Csr(a.n, a.row_ptr, a.col_idx, a.vals * 1e200)
+    b = W.rhs_normal(a.n, 4)
+    print("non-finite mid-solve", flush=True)
+    s = Solver(big)
+    try:
+        bd = s.to_device(b)
+        x = torch.zeros_like(bd)
+        with pytest.raises(igs.IgsError) as e:
+            igs.igs_solve_opts(s.ctx, bd, x, 10, 1e-12, 2, igs.IgsOpts())
+        assert e.value.code == igs.IGS_ENUMERIC
+        assert "non-finite" in igs.igs_last_error(s.ctx)
+        assert torch.all(x == 0).item()
+        # the context stays usable: a zero right-hand side converges at once
+        rc, info = igs.igs_solve_opts(s.ctx, torch.zeros_like(bd), x, 10, 1e-12, 2, igs.IgsOpts())
+        assert rc == 0 and info["iters"] == 0
+    finally:
+        s.close()
+
+
 def test_maxit_returns_enoconv(torch):
     from paper_2205_07805_amd import igs
     a = W.convdiff2d(12, 20.0)
