@@ -148,7 +148,9 @@ def test_lagnorm_guard_forced_many_update_blocks(torch, fp32):
     assert info["iters"] == ref.iters == 6
     assert info["lagnorm_fallbacks"] == ref.lagnorm_fallbacks == 6
     assert info["first_cycle_J"] == ref.first_cycle.J == 1
-    assert info["last_cycle_status"] == "lagnorm"
+    # the six cycles each ended at the fallback (six fallbacks, six
+    # iterations); the check cycle after the cycle budget ends the solve
+    assert info["last_cycle_status"] == "maxit"
     # column 0 of the first cycle: H[0,0] from the reduction, H[1,0] the explicit norm
     htol = 1e-6 if fp32 else 1e-11
     assert np.linalg.norm(H[:2, 0] - ref.first_cycle.H[:2, 0]) <= htol * np.linalg.norm(ref.first_cycle.H[:2, 0])
