@@ -362,6 +362,37 @@ int igs_kernel_reduce(igs_ctx *ctx, const double *V, int64_t ldv, int j,
 int igs_kernel_update(igs_ctx *ctx, double *V, int64_t ldv, int j, const double *z,
                       const double *t_host, const double *r1_host, double inv_gamma);
 
+/* ---- Without allocation ---------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * igs_kernel_reduce without a context: the same kernel and launch shape, so
+ * the same sums bit for bit, with its per-block partial sums, group totals
+ * and arrival counters in a static device array of the library
+ * (IGS_NOALLOC_BYTES on each GPU it runs on, held until the process ends)
+ * instead of a workspace:
+ *   PQ[c]         = V[:, c]^T u   (u = V[:, j]),
+ *   PQ[j + 1 + c] = V[:, c]^T z   (0 when z is NULL),   c = 0..j.
+ * V: device, column-major, ldv >= n >= 1, j + 1 columns; z: device float64[n]
+ * or NULL; PQ: device float64[2 (j + 1)], written by the call.
+ * 0 <= j < IGS_NOALLOC_MAX_COLS.  hip_stream: a stream of the current
+ * device (NULL: its null stream).
+ * Asynchronous: returns once the work is queued (no synchronisation, no
+ * memset: a counter-clearing kernel and the reduction), so a caller may
+ * record it into a graph.  The first call on a device also looks up the
+ * array's device address and the occupancy of every reduction shape; make
+ * that first call outside a capture.
+ * Every call on one GPU shares that GPU's array and leaves it holding its own
+ * sums: calls that overlap on one GPU (other streams, other host threads)
+ * race and must be serialised by the caller.
+ * Errors: IGS_EINVAL (NULL V or PQ, n < 1, ldv < n, j out of range; checked
+ * before any device call), IGS_EDEVICE (a launch failed).  The message is
+ * igs_last_error(NULL). */
+#define IGS_NOALLOC_MAX_COLS 256
+#define IGS_NOALLOC_BYTES ((2048 + 64) * 2 * IGS_NOALLOC_MAX_COLS * 8 + 512)
+int igs_kernel_reduce_noalloc(const double *V, int64_t ldv, int64_t n, int j,
+                              const double *z, double *PQ, void *hip_stream);
+
 /* ---- Per-kernel timing (opts.profile = 1) --------------------------------- */
 
 enum { IGS_K_SPMV = 0, IGS_K_REDUCE = 1, IGS_K_UPDATE = 2, IGS_K_XUPDATE = 3,

@@ -155,6 +155,14 @@ hipError_t launch_mgs_column(const Work& w, long long n, int c, hipStream_t s);
 hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j, const double* z,
                              double* part, double* gpart, int pstride, unsigned* tickets,
                              double* out, hipStream_t s);
+// The same reduction with its partial sums and counters in the library's
+// static device array (no allocation; calls overlapping on one device race).
+// Columns j + 1 <= kNoAllocMaxCols; out: device, 2 (j + 1) doubles.
+constexpr int kNoAllocMaxCols = 256;
+constexpr size_t kNoAllocBytes =
+    ((size_t)(kMaxBlocks + kMaxGroups) * 2 * kNoAllocMaxCols + 64) * sizeof(double);
+hipError_t launch_reduce_noalloc(const double* V, long long ldv, long long n, int j,
+                                 const double* z, double* out, hipStream_t s);
 hipError_t launch_update_raw(double* V, long long ldv, long long n, int j, const double* z,
                              const double* t, const double* r1, double inv_gamma, hipStream_t s);
 

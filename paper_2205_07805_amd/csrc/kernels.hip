@@ -1512,6 +1512,81 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
 }
 
 // ---------------------------------------------------------------------------
+// The fused reduction without allocation
+// ---------------------------------------------------------------------------
+//
+// Its per-block partial sums, group totals and arrival counters live in one
+// static device array of the library instead of a workspace.  The array's
+// name is a host-side stand-in in host code: its address on each device is
+// taken once with hipGetSymbolAddress and only that address reaches kernels.
+
+constexpr int kNoAllocStride = 2 * kNoAllocMaxCols;   // doubles per partial-sum row
+constexpr size_t kNoAllocPartDoubles = (size_t)kMaxBlocks * kNoAllocStride;
+constexpr size_t kNoAllocGroupDoubles = (size_t)kMaxGroups * kNoAllocStride;
+constexpr size_t kNoAllocCounterDoubles = 64;          // kMaxGroups + 1 counters, padded
+constexpr size_t kNoAllocDoubles = kNoAllocPartDoubles + kNoAllocGroupDoubles + kNoAllocCounterDoubles;
+static_assert((kMaxGroups + 1) * sizeof(unsigned) <= kNoAllocCounterDoubles * sizeof(double),
+              "counter area too small");
+static_assert(kNoAllocDoubles * sizeof(double) == kNoAllocBytes, "scratch size mismatch");
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kNoAllocMaxDevices = 64;
+
+struct NoAllocDevice {
+  std::once_flag once;
+  hipError_t err = hipSuccess;
+  double* ptr = nullptr;   // the device address of `scratch` on this device
+};
+static NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+// Zero the arrival counters (a kernel, not a memset, so that the call can be
+// recorded into a HIP graph and replayed).
+__global__ void clear_counters_kernel(unsigned* c, int count) {
+  if ((int)threadIdx.x < count) c[threadIdx.x] = 0u;
+}
+
+hipError_t launch_reduce_noalloc(const double* V, long long ldv, long long n, int j,
+                                 const double* z, double* out, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  NoAllocDevice& d = g_noalloc[dev];
+  // Once per device, with that device current: the array's address there, and
+  // the occupancy queries of every reduction shape this entry point can
+  // launch, so that later calls only queue kernels.
+  std::call_once(d.once, [&] {
+    void* p = nullptr;
+    d.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (d.err != hipSuccess) return;
+    d.ptr = static_cast<double*>(p);
+    for (int ncol = 1; ncol <= kNoAllocMaxCols; ++ncol) {
+      const ReduceShape sh = reduce_columns(ncol);
+      const size_t lds = reduce_lds_bytes(sh, ncol);
+      for (int vec = 0; vec < 2; ++vec)
+        (void)resident_blocks(reinterpret_cast<const void*>(pick_reduce<double>(sh.tcpw, vec, true)),
+                              kReduceThreads, lds);
+    }
+    (void)resident_blocks(nullptr, 0, 0);
+  });
+  if (d.err != hipSuccess) return d.err;
+  if (d.ptr == nullptr) return hipErrorInvalidSymbol;
+  double* part = d.ptr;
+  double* gpart = d.ptr + kNoAllocPartDoubles;
+  unsigned* tickets = reinterpret_cast<unsigned*>(d.ptr + kNoAllocPartDoubles + kNoAllocGroupDoubles);
+  hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(128), 0, s, tickets, kMaxGroups + 1);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  Work w{};
+  w.part = part;
+  w.gpart = gpart;
+  w.pstride = kNoAllocStride;
+  w.tickets = tickets;
+  return reduce_dispatch<double>(w, n, j, z != nullptr, V, ldv, z, out, s, nullptr);
+}
+
+// ---------------------------------------------------------------------------
 // Basis update: one pass over V_{0:j}
 // ---------------------------------------------------------------------------
 

@@ -937,6 +937,24 @@ extern "C" int igs_kernel_update(igs_ctx* c, double* V, int64_t ldv, int j, cons
   return IGS_OK;
 }
 
+static_assert(igs::kNoAllocMaxCols == IGS_NOALLOC_MAX_COLS, "no-allocation column limit");
+static_assert(igs::kNoAllocBytes == (size_t)IGS_NOALLOC_BYTES, "no-allocation scratch size");
+
+extern "C" int igs_kernel_reduce_noalloc(const double* V, int64_t ldv, int64_t n, int j,
+                                         const double* z, double* PQ, void* hip_stream) {
+  // every check before the first device call
+  if (!V || !PQ) return set_err(nullptr, IGS_EINVAL, "V and PQ must be device pointers");
+  if (n < 1 || ldv < n) return set_err(nullptr, IGS_EINVAL, "need n >= 1 and ldv >= n");
+  if (j < 0 || j >= IGS_NOALLOC_MAX_COLS)
+    return set_err(nullptr, IGS_EINVAL, "j = %d: the no-allocation reduction takes 0 <= j < %d",
+                   j, IGS_NOALLOC_MAX_COLS);
+  const hipError_t e = igs::launch_reduce_noalloc(V, ldv, n, j, z, PQ,
+                                                  static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess)
+    return set_err(nullptr, IGS_EDEVICE, "igs_kernel_reduce_noalloc: %s", hipGetErrorString(e));
+  return IGS_OK;
+}
+
 extern "C" int igs_profile_get(igs_ctx* c, int which, int64_t* launches, double* total_ms,
                                double* total_bytes) {
   if (!c || which < 0 || which >= IGS_K_COUNT) return IGS_EINVAL;

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libigs.so")
 IGS_OK, IGS_ENOCONV, IGS_EINVAL, IGS_ENOMEM, IGS_EDEVICE, IGS_ENOTIMPL, IGS_ENUMERIC = 0, 1, -1, -2, -3, -4, -5
 IGS_MAX_RESTART = 512
 IGS_MAX_BATCH = 32
+IGS_NOALLOC_MAX_COLS = 256
+IGS_NOALLOC_BYTES = (2048 + 64) * 2 * IGS_NOALLOC_MAX_COLS * 8 + 512
 (IGS_K_SPMV, IGS_K_REDUCE, IGS_K_UPDATE, IGS_K_XUPDATE, IGS_K_RESIDUAL, IGS_K_COUNT) = range(6)
 KERNEL_NAMES = ("spmv", "reduce", "update", "xupdate", "residual")
 CYCLE_STATUS = ("running", "converged_at_start", "arnoldi_converged", "full", "breakdown",
@@ -27,6 +29,7 @@ EXPORTED = (
     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
     "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
     "igs_serve", "igs_solve_batch", "igs_serve_batched", "igs_tune", "igs_tune_reset",
+    "igs_kernel_reduce_noalloc",
 )
 
 
@@ -96,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "igs_kernel_spmv": (c_int, [P, P, P]),
         "igs_kernel_reduce": (c_int, [P, P, c_int64, c_int, P, P, P]),
         "igs_kernel_update": (c_int, [P, P, c_int64, c_int, P, P, P, c_double]),
+        "igs_kernel_reduce_noalloc": (c_int, [P, c_int64, c_int64, c_int, P, P, P]),
         "igs_profile_get": (c_int, [P, c_int, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
         "igs_profile_reset": (c_int, [P]),
         "igs_serve": (c_int, [POINTER(IgsRequest), c_int, c_int, c_int64, c_int, c_double, c_int,
@@ -207,6 +211,13 @@ def igs_kernel_update(ctx, V, ldv, j, z, t_host, r1_host, inv_gamma) -> None:
     _check("igs_kernel_update", load_library().igs_kernel_update(
         ctx, _ptr(V), int(ldv), int(j), _ptr(z), _ptr(t_host), _ptr(r1_host),
         float(inv_gamma)), ctx)
+
+
+def igs_kernel_reduce_noalloc(V, ldv, n, j, z, PQ, hip_stream=None) -> None:
+    """Queues the reduction on hip_stream (a torch stream's cuda_stream, or
+    None for the null stream) and returns without waiting."""
+    _check("igs_kernel_reduce_noalloc", load_library().igs_kernel_reduce_noalloc(
+        _ptr(V), int(ldv), int(n), int(j), _ptr(z), _ptr(PQ), _ptr(hip_stream)), None)
 
 
 def igs_profile_get(ctx, which):

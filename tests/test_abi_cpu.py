@@ -145,3 +145,30 @@ def test_batch_entry_points_reject_bad_arguments_without_gpu_work(lib):
     assert L.igs_serve_batched(reqs, 1, 4, 1 << 30, 10, 1e-10, 2, ctypes.byref(o), None) == \
         igs.IGS_ENOTIMPL
     assert L.igs_serve_batched(reqs, 1, 4, 1024, 10, 1e-10, 2, None, None) == igs.IGS_EINVAL
+
+
+def test_noalloc_reduce_checks_sizes_before_any_device_call(lib):
+    """Out-of-range sizes and NULL buffers are refused before the library
+    touches a device (the fake addresses are never dereferenced)."""
+    from paper_2205_07805_amd import igs
+    fake = 4096
+    cases = ((8, 8, igs.IGS_NOALLOC_MAX_COLS), (8, 8, -1), (0, 8, 0), (8, 4, 0))
+    for n, ldv, j in cases:
+        with pytest.raises(igs.IgsError) as e:
+            igs.igs_kernel_reduce_noalloc(fake, ldv, n, j, None, fake)
+        assert e.value.code == igs.IGS_EINVAL, (n, ldv, j)
+        assert "no-allocation" in e.value.args[0] or "n >= 1" in e.value.args[0]
+    for V, PQ in ((None, fake), (fake, None)):
+        with pytest.raises(igs.IgsError) as e:
+            igs.igs_kernel_reduce_noalloc(V, 8, 8, 0, None, PQ)
+        assert e.value.code == igs.IGS_EINVAL
+
+
+def test_noalloc_limits_match_the_header():
+    from paper_2205_07805_amd import igs
+    text = open(HEADER).read()
+    cols = int(re.search(r"#define IGS_NOALLOC_MAX_COLS (\d+)", text).group(1))
+    assert cols == igs.IGS_NOALLOC_MAX_COLS
+    expr = re.search(r"#define IGS_NOALLOC_BYTES (.+)", text).group(1).replace(
+        "IGS_NOALLOC_MAX_COLS", str(cols))
+    assert eval(expr) == igs.IGS_NOALLOC_BYTES  # a plain integer expression of the header
