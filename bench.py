@@ -72,31 +72,63 @@ def backward_error_torch(torch, a, b_d, x_d, iters=60):
     return float(r.norm()) / (float(b_d.norm()) + est * float(x_d.norm())), est
 
 
-def cpu_baseline(a, b, restart, tol, n_iters):
-    """The FP64 oracle (one-reduce IGS-GMRES, two sweeps) on the host: the same
-    solve, stopped after n_iters Arnoldi iterations (whole restart cycles)."""
-    import oracle
-    threads = None
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = None
     try:
-        from threadpoolctl import threadpool_info
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_rate(a, b, restart, tol, n_iters, threads=None):
+    """Arnoldi iterations per second of the FP64 oracle (one-reduce, two
+    sweeps) over the first n_iters iterations of the solve (whole cycles),
+    with numpy's BLAS limited to `threads` (None: its default), and the
+    thread count it used."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    with threadpool_limits(limits=threads):
         info = threadpool_info()
-        threads = max((i.get("num_threads") or 1) for i in info) if info else 1
-    except Exception:
-        threads = os.cpu_count()
-    t0 = time.perf_counter()
-    res = oracle.gmres(a, b, restart=restart, tol=tol, variant="igs1r", gs_iters=2, maxit=n_iters)
-    dt = time.perf_counter() - t0
-    return {"value": res.iters / dt, "unit": "Arnoldi iters/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"first {res.iters} Arnoldi iterations ({res.iters // restart} GMRES({restart}) "
-                      f"cycles, one-reduce, two sweeps) of the same {a.n}-row solve, {dt:.1f} s"}
+        used = max((i.get("num_threads") or 1) for i in info) if info else 1
+        t0 = time.perf_counter()
+        res = oracle.gmres(a, b, restart=restart, tol=tol, variant="igs1r", gs_iters=2,
+                           maxit=n_iters)
+        dt = time.perf_counter() - t0
+    return res.iters / dt, int(used), res.iters, dt
 
 
-def mixed_precision_compare(torch, W, Solver, igs, dev, steps, grid=96, restart=40, tol=5e-14):
+def cpu_baseline(a, b, restart, tol, n_iters, n_iters_single):
+    """The FP64 oracle on the host: the same solve, stopped after n_iters
+    Arnoldi iterations on all the BLAS threads, and after n_iters_single on
+    one thread."""
+    rate, used, its, dt = oracle_rate(a, b, restart, tol, n_iters)
+    rate1, _, its1, dt1 = oracle_rate(a, b, restart, tol, n_iters_single, threads=1)
+    return {"value": rate, "unit": "Arnoldi iters/s", "cores": used, "kind": "oracle",
+            "sample": f"first {its} Arnoldi iterations ({its // restart} GMRES({restart}) "
+                      f"cycles, one-reduce, two sweeps) of the same {a.n}-row solve, {dt:.1f} s "
+                      f"on {used} BLAS threads",
+            "single_thread": {"value": rate1, "unit": "Arnoldi iters/s", "cores": 1,
+                              "sample": f"first {its1} Arnoldi iterations, {dt1:.1f} s"},
+            **host_cpu()}
+
+
+def mixed_precision_compare(torch, W, Solver, igs, dev, steps, grid=96, restart=40, tol=5e-14,
+                            with_oracle=True):
     """Solves per second of GMRES(restart) on the 3D convection-diffusion
     system of side `grid` to tol (backward error about 7e-15), with FP64
     cycles and with FP32 cycles inside FP64 restarts (iterative refinement).
-    The error of the FP32-cycle solution is stated against the FP64 one."""
+    Each solution's error is stated against the GPU's FP64 one and (with
+    with_oracle) against the FP64 oracle's solve on the host."""
     a, b = W.make_convdiff3d(grid, 50.0)
     s = Solver(a)
     b_d = torch.as_tensor(b, device=dev)
@@ -124,14 +156,25 @@ def mixed_precision_compare(torch, W, Solver, igs, dev, steps, grid=96, restart=
                          "solves_per_s": 1.0 / dt, "iters_per_s": info["iters"] / dt,
                          "backward_error": beta}
         out["speedup"] = out["fp64"]["ms_per_solve"] / out["fp32_cycles"]["ms_per_solve"]
-        out["fp32_cycles_vs_fp64_max_rel_diff"] = float(
+        out["fp32_cycles_vs_gpu_fp64_max_rel_diff"] = float(
             (xs["fp32_cycles"] - xs["fp64"]).abs().max() / xs["fp64"].abs().max())
+        if with_oracle:
+            # each result against the FP64 oracle's solve of the same system
+            import oracle
+            t0 = time.perf_counter()
+            ref = oracle.gmres(a, b, restart=restart, tol=tol, variant="igs1r", gs_iters=2,
+                               maxit=20000)
+            xr = torch.as_tensor(ref.x, device=dev)
+            out["vs_fp64_oracle"] = {
+                "oracle_iters": ref.iters, "oracle_seconds": time.perf_counter() - t0,
+                **{f"{k}_max_rel_diff": float((xs[k] - xr).abs().max() / xr.abs().max())
+                   for k in ("fp64", "fp32_cycles")}}
     finally:
         s.close()
     return out
 
 
-def other_configs(torch, W, Solver, igs, steps=5):
+def other_configs(torch, W, Solver, igs, steps=5, oracle_small=True):
     """The two other single-solve configurations, timed the same way as the
     bench line: the small 2D system (n = 1,024, GMRES(50), tol 1e-12; also
     with its cycles replayed from a HIP graph), and one full GMRES(200) cycle
@@ -166,12 +209,18 @@ def other_configs(torch, W, Solver, igs, steps=5):
                          "ms_per_solve": 1e3 * dt, "iters_per_s": info["iters"] / dt,
                          "us_per_iter": 1e6 * dt / max(info["iters"], 1),
                          "relres_true": info["relres_true"]}
+            if oracle_small and name == cases[0][0]:
+                # the oracle's whole solve of the same system on the host
+                rate, used, its, odt = oracle_rate(a, b, restart, tol, 20 * len(b))
+                out[name]["oracle_cpu"] = {"iters": its, "ms_per_solve": 1e3 * odt,
+                                           "iters_per_s": rate, "cores": used, "kind": "oracle"}
         finally:
             s.close()
     return out
 
 
-def serving_compare(W, serve, count, slots, batch, mem_cap=64 << 30, restart=50, tol=1e-12):
+def serving_compare(W, serve, count, slots, batch, mem_cap=64 << 30, restart=50, tol=1e-12,
+                    rate=200.0, legs_wanted=None):
     """The serving trace (2D convection-diffusion, sides uniform on [32, 512],
     Pe uniform on [1, 100], Poisson arrivals at 200/s, b seeded per request)
     served four ways: the plain FP64 solver one request at a time (a queue
@@ -183,7 +232,7 @@ def serving_compare(W, serve, count, slots, batch, mem_cap=64 << 30, restart=50,
     is checked on the host with scipy (relres <= tol implies backward error
     <= tol)."""
     import scipy.sparse as sp
-    trace = W.serving_trace(count=count, seed=7)
+    trace = W.serving_trace(count=count, seed=7, rate=rate)
 
     def solve_bytes(q, iters, es):
         # algorithmic HBM bytes of `iters` Arnoldi iterations, cycles of
@@ -199,13 +248,16 @@ def serving_compare(W, serve, count, slots, batch, mem_cap=64 << 30, restart=50,
 
     systems = [(q.a, q.b, q.arrival) for q in trace]
     mats = [sp.csr_matrix((q.a.vals, q.a.col_idx, q.a.row_ptr), shape=(q.a.n, q.a.n)) for q in trace]
-    out = {"workload": f"{W.SERVING.name}_{count}req_gmres{restart}_tol{tol:g}",
+    wl = W.SERVING.name if rate == 200.0 else W.SERVING.name.replace("poisson200", f"poisson{rate:g}")
+    out = {"workload": f"{wl}_{count}req_gmres{restart}_tol{tol:g}", "arrival_rate_per_s": rate,
            "requests": count, "slots": slots, "batch": batch, "mem_cap_bytes": mem_cap,
            "n_range": [min(q.a.n for q in trace), max(q.a.n for q in trace)],
            "arrival_window_s": trace[-1].arrival}
     legs = (("fp64_serial", dict(slots=1), 0), ("fp64_streams", dict(slots=slots), 0),
             ("fp64_batch_kernels", dict(batch=batch), 0),
             ("fp32_cycles_batch_kernels", dict(batch=batch), 1))
+    if legs_wanted:
+        legs = tuple(l for l in legs if l[0] in legs_wanted)
     for name, how, fp32 in legs:
         res, wall, rc = serve(systems, mem_cap=mem_cap, restart=restart, tol=tol, gs_iters=2,
                               inner_fp32=fp32, maxit=200000, **how)
@@ -221,9 +273,10 @@ def serving_compare(W, serve, count, slots, batch, mem_cap=64 << 30, restart=50,
                      "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
                      "max_relres": rel}
         log(f"[bench] serving {name}: {out[name]}")
-    base = out["fp64_serial"]["solves_per_s"]
-    for name, _, _ in legs[1:]:
-        out[name]["throughput_vs_fp64_serial"] = out[name]["solves_per_s"] / base
+    if "fp64_serial" in out:
+        base = out["fp64_serial"]["solves_per_s"]
+        for name, _, _ in legs[1:]:
+            out[name]["throughput_vs_fp64_serial"] = out[name]["solves_per_s"] / base
     return out
 
 
@@ -244,6 +297,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-batch", type=int, default=32)
+    ap.add_argument("--sustained-rate", type=float, default=10.0,
+                    help="arrivals per second of the serving point the GPU sustains")
+    ap.add_argument("--sustained-requests", type=int, default=128)
+    ap.add_argument("--cpu-iters-single", type=int, default=60)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -298,7 +355,8 @@ def main():
         rc, info = solve(2, profile_kernels=0)
         log(f"[bench] warmup: rc={rc} iters={info['iters']} relres={info['relres_true']:.2e}")
     warm = kernel_table(s.profile()) if not args.no_profile else {}
-    dominant = max(("spmv", "reduce", "update"), key=lambda k: warm.get(k, {}).get("ms", 0.0))
+    dominant = max(("spmv", "opreduce", "reduce", "update"),
+                   key=lambda k: warm.get(k, {}).get("ms", 0.0))
     dom_mask = 1 << igs.KERNEL_NAMES.index(dominant)
     s.profile_reset()
     torch.cuda.synchronize()
@@ -363,11 +421,12 @@ def main():
     mixed = None
     if not args.no_mixed:
         log("[bench] mixed precision on 96^3 ...")
-        mixed = mixed_precision_compare(torch, W, Solver, igs, dev, args.mixed_steps)
+        mixed = mixed_precision_compare(torch, W, Solver, igs, dev, args.mixed_steps,
+                                        with_oracle=not args.no_cpu_baseline)
         log(f"[bench] mixed: {mixed}")
     s.close()
 
-    others = other_configs(torch, W, Solver, igs)
+    others = other_configs(torch, W, Solver, igs, oracle_small=not args.no_cpu_baseline)
     log(f"[bench] other configurations: {others}")
 
     serving = None
@@ -376,12 +435,19 @@ def main():
         log(f"[bench] serving {args.serve_requests} requests ...")
         serving = serving_compare(W, serve, args.serve_requests, args.serve_slots,
                                   args.serve_batch)
+        # the same kind of trace at an arrival rate well inside what the GPU
+        # serves, so that latency is service time rather than queue drain
+        log(f"[bench] serving at {args.sustained_rate:g}/s ...")
+        serving["sustained"] = serving_compare(
+            W, serve, args.sustained_requests, args.serve_slots, args.serve_batch,
+            rate=args.sustained_rate, legs_wanted=("fp64_batch_kernels", "fp32_cycles_batch_kernels"))
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(a, b, args.restart, args.tol, args.cpu_iters)
-        log(f"[bench] cpu baseline: {cpu['value']:.2f} iters/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(a, b, args.restart, args.tol, args.cpu_iters, args.cpu_iters_single)
+        log(f"[bench] cpu baseline: {cpu['value']:.2f} iters/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.2f} on one ({cpu['cpu_model']})")
 
     line = {
         "metric": METRIC,

@@ -96,7 +96,13 @@ typedef struct igs_opts {
                            w = u - V r3 and the column r1 + r3; two global
                            reductions per iteration (a comparator for the
                            one-reduce default)                                 */
-  int reserved[1];
+  int separate_apply;   /* 1: the operator apply as a kernel of its own before
+                           the reduction.  By default, with an ELL form (rows
+                           of at most 8 entries) and n a multiple of 4, each
+                           block of the reduction forms its own rows of A u
+                           first (one launch and one read of u and of A u
+                           less per iteration); the results are
+                           bit-identical either way.                        */
   double inner_rtol;    /* inner_fp32: a cycle also ends once its Arnoldi
                            residual is <= inner_rtol * ||r0|| of the cycle;
                            <= 0 means 1e-5                                     */
@@ -341,6 +347,16 @@ int igs_debug_copy_H(igs_ctx *ctx, double *H_host, int ldh, int *ncols);
  * Needs opts.keep_first_basis = 1 in the last solve, else IGS_EINVAL. */
 int igs_debug_copy_V(igs_ctx *ctx, double *V_dev, int64_t ldv, int *ncols);
 
+/* Estimate of ||A||_2 from the last solve (the backward error's
+ * denominator, eq:nrbe): the largest singular value of the first cycle's
+ * (J+1) x J Hessenberg matrix, computed on the host from the copy the solve
+ * keeps (Lanczos on H^T H, exact for J <= 100).  With the orthonormal basis,
+ * A V_J = V_{J+1} H (Section 1, the Arnoldi relation), so it equals
+ * ||A V_J||_2, a lower bound of ||A||_2; a backward error formed with it is
+ * an upper bound.  Not part of the solve's time.  Errors: IGS_EINVAL when the
+ * first cycle finished no column. */
+int igs_anorm_estimate(igs_ctx *ctx, double *anorm_out);
+
 /* ---- Step kernels on caller buffers (unit tests of each hot-path step) --- */
 
 /* z = A u with the context's operator kernel.  u, z: device float64[n]. */
@@ -396,7 +412,9 @@ int igs_kernel_reduce_noalloc(const double *V, int64_t ldv, int64_t n, int j,
 /* ---- Per-kernel timing (opts.profile = 1) --------------------------------- */
 
 enum { IGS_K_SPMV = 0, IGS_K_REDUCE = 1, IGS_K_UPDATE = 2, IGS_K_XUPDATE = 3,
-       IGS_K_RESIDUAL = 4, IGS_K_COUNT = 5 };
+       IGS_K_RESIDUAL = 4,
+       IGS_K_OPREDUCE = 5,   /* the operator apply fused into the reduction */
+       IGS_K_COUNT = 6 };
 
 /* Totals over the timed launches of kernel `which` since the last reset:
  * launches, summed HIP-event milliseconds, and summed algorithmic bytes

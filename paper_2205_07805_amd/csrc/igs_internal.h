@@ -134,6 +134,15 @@ hipError_t launch_bnorm(const double* b, const double* x, long long n, const Wor
                         hipStream_t s);
 hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,
                          int* nblocks_out);
+// The operator apply fused into the reduction (z = A u_j for each block's own
+// rows, then the reduction with z from shared memory; z is also stored for
+// the update).  opreduce_fits: whether iteration j can take it (an ELL form,
+// n a multiple of 4, aligned arrays, a block's rows of z within its shared
+// memory); otherwise launch_spmv* and launch_reduce run as two kernels.  The
+// results are bit-identical either way.
+bool opreduce_fits(const Op& op, const Work& w, long long n, int j);
+hipError_t launch_opreduce(const Op& op, const Work& w, long long n, int j, hipStream_t s,
+                           int* nblocks_out);
 // ngroups: the group totals the reduction of iteration j left in w.gpart.
 hipError_t launch_update(const Work& w, long long n, int j, int gs, int ngroups, hipStream_t s);
 // Second Gauss-Seidel sweep of the two-reduce variant for the vector in

@@ -1194,8 +1194,8 @@ static void reduce_rows(ReduceShape& s, long long n, int max_blocks) {
 template <int NC, bool VEC, bool Z, typename T>
 __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long ldv,
                                             const T* __restrict__ u, const T* __restrict__ z,
-                                            long long r0, long long r1, int rw, int wr, int lane,
-                                            double* ap, double* aq) {
+                                            long long zoff, long long r0, long long r1, int rw,
+                                            int wr, int lane, double* ap, double* aq) {
   if constexpr (VEC) {
     // Lane owns W consecutive rows (one 16-byte load per column; V
     // non-temporal).  Two-stage software pipeline: the loads of the next row
@@ -1216,7 +1216,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
     for (int c = 0; c < NC; ++c) va[c] = vn[c] = ua;
     auto load = [&](VT& uu, VT& zz, VT* vv, long long rr) {
       uu = ld16<T>(u + rr);
-      if constexpr (Z) zz = ld16<T>(z + rr);
+      if constexpr (Z) zz = ld16<T>(z + (rr - zoff));
 #pragma unroll
       for (int c = 0; c < NC; ++c) vv[c] = ld16_stream<T>(vb + (size_t)c * ldv + rr);
     };
@@ -1245,7 +1245,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
     // the last rows of the block's range that do not fill a vector
     for (long long rr = r; rr < r1 && rr < r + W; ++rr) {
       const double uv = (double)u[rr];
-      const double zv = Z ? (double)z[rr] : 0.0;
+      const double zv = Z ? (double)z[rr - zoff] : 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double v = (double)vb[(size_t)c * ldv + rr];
@@ -1263,7 +1263,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         uu[q] = (double)u[r + q * step];
-        if constexpr (Z) zz[q] = (double)z[r + q * step];
+        if constexpr (Z) zz[q] = (double)z[r + q * step - zoff];
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
@@ -1281,7 +1281,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
     }
     for (; r < r1; r += step) {
       const double uv = (double)u[r];
-      const double zv = Z ? (double)z[r] : 0.0;
+      const double zv = Z ? (double)z[r - zoff] : 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double v = (double)vb[(size_t)c * ldv + r];
@@ -1297,22 +1297,22 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
 template <int CPW, bool VEC, bool Z, typename T>
 __device__ __forceinline__ void stream_group(int nc, const T* __restrict__ vb, long long ldv,
                                              const T* __restrict__ u,
-                                             const T* __restrict__ z, long long r0,
-                                             long long r1, int rw, int wr, int lane, double* ap,
-                                             double* aq) {
+                                             const T* __restrict__ z, long long zoff,
+                                             long long r0, long long r1, int rw, int wr,
+                                             int lane, double* ap, double* aq) {
   if (nc == CPW) {
-    stream_cols<CPW, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq);
+    stream_cols<CPW, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq);
     return;
   }
   if constexpr (CPW > 1) {
     switch (nc) {
-      case 1: stream_cols<1, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 2: if constexpr (CPW > 2) stream_cols<2, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 3: if constexpr (CPW > 3) stream_cols<3, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 4: if constexpr (CPW > 4) stream_cols<4, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 5: if constexpr (CPW > 5) stream_cols<5, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 6: if constexpr (CPW > 6) stream_cols<6, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
-      case 7: if constexpr (CPW > 7) stream_cols<7, VEC, Z, T>(vb, ldv, u, z, r0, r1, rw, wr, lane, ap, aq); break;
+      case 1: stream_cols<1, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 2: if constexpr (CPW > 2) stream_cols<2, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 3: if constexpr (CPW > 3) stream_cols<3, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 4: if constexpr (CPW > 4) stream_cols<4, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 5: if constexpr (CPW > 5) stream_cols<5, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 6: if constexpr (CPW > 6) stream_cols<6, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 7: if constexpr (CPW > 7) stream_cols<7, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
       default: break;
     }
   }
@@ -1326,22 +1326,27 @@ template <typename T> __host__ __device__ T* zvec(const Work& w);
 template <> __host__ __device__ double* zvec<double>(const Work& w) { return w.z; }
 template <> __host__ __device__ float* zvec<float>(const Work& w) { return w.z32; }
 
-template <int CPW, bool VEC, bool Z, typename T>
+// ZS: z is the block's own rows of A u in shared memory (zsh[r - r0]), formed
+// by the fused operator apply; sm: the shared memory of the reduction (the
+// dynamic shared memory when null).
+template <int CPW, bool VEC, bool Z, typename T, bool ZS = false>
 __device__ __forceinline__ void reduce_body(
     Grid gr, const Work& w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr,
     const T* __restrict__ Vraw, long long ldv_raw, const T* __restrict__ zraw,
-    double* __restrict__ raw_out) {
-  extern __shared__ double lds[];
+    double* __restrict__ raw_out, double* sm = nullptr, const T* zsh = nullptr) {
+  extern __shared__ double dyn_lds[];
+  double* lds = ZS ? sm : dyn_lds;
   const bool raw = (raw_out != nullptr);
-  if (!raw && !ctl_runs(w.ctl, j)) return;
+  if (!ZS && !raw && !ctl_runs(w.ctl, j)) return;
   const T* __restrict__ V = raw ? Vraw : basis<T>(w);
   const long long ldv = raw ? ldv_raw : w.ldv;
-  const T* __restrict__ z = raw ? zraw : zvec<T>(w);
   const int ncol = j + 1;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const long long r0 = (long long)gr.bid * rows_per_block;
   const long long r1 = min(n, r0 + rows_per_block);
+  const T* __restrict__ z = ZS ? zsh : (raw ? zraw : zvec<T>(w));
+  const long long zoff = ZS ? r0 : 0;
   const T* __restrict__ u = V + (size_t)j * ldv;
   const int nchunk = (ncol + cpw - 1) / cpw;
   const int cw = wave % wc;
@@ -1353,8 +1358,8 @@ __device__ __forceinline__ void reduce_body(
       double ap[CPW], aq[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
-      stream_group<CPW, VEC, Z, T>(nc, V + (size_t)c0 * ldv, ldv, u, z, r0, r1, rw, wr, lane, ap,
-                                   aq);
+      stream_group<CPW, VEC, Z, T>(nc, V + (size_t)c0 * ldv, ldv, u, z, zoff, r0, r1, rw, wr,
+                                   lane, ap, aq);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         if (c < nc) {
@@ -1509,6 +1514,183 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
   w.pstride = pstride;
   w.tickets = tickets;
   return reduce_dispatch<double>(w, n, j, z != nullptr, V, ldv, z, out, s, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply fused into the reduction: A u, then [V_{0:j}, u]^T [u, A u]
+// ---------------------------------------------------------------------------
+//
+// With the operator in ELL form, each block of the fused reduction first forms
+// z = A u for its own rows, keeps them in shared memory for V^T z and stores
+// them for the update kernel; then it runs the reduction of reduce_body on the
+// same grid.  Against the operator apply and the reduction as two kernels,
+// u is read once and z is never read back from device memory, and the
+// iteration has one launch less.  z is bit-identical to the ELL (and CSR)
+// kernel's: every row's products and additions are theirs, in their order,
+// with contraction off; the reduction then adds the same values in the same
+// order, so its sums are bit-identical too.
+
+// Four consecutive rows r .. r+3 of z = A x from the column-major ELL form
+// (entry slot k of row r at k n + r; K <= 8 slots): each slot's column indices
+// and values are read as one vector of four.  Needs n and r multiples of 4
+// and 16-byte aligned arrays (32-byte for FP64 values).
+template <typename T>
+__device__ __forceinline__ void ell_rows4(const int* __restrict__ col, const T* __restrict__ val,
+                                          long long n, int K, const T* __restrict__ x,
+                                          long long r, T* out) {
+#pragma clang fp contract(off)
+  typedef int I4 __attribute__((ext_vector_type(4)));
+  typedef T A4 __attribute__((ext_vector_type(4)));
+  I4 c[8];
+  A4 v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < K) {
+      c[k] = *reinterpret_cast<const I4*>(col + (long long)k * n + r);
+      v[k] = *reinterpret_cast<const A4*>(val + (long long)k * n + r);
+    } else {
+      c[k] = I4(0);
+      v[k] = A4(0);
+    }
+  }
+  T g[8][4];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[k][i] = x[c[k][i]];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T p[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = v[k][i] * g[k][i];
+    const T q0 = (p[0] + p[1]) + (p[2] + p[3]);
+    const T q1 = (p[4] + p[5]) + (p[6] + p[7]);
+    out[i] = q0 + q1;
+  }
+}
+
+template <int CPW, typename T>
+__global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
+    Work w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr, int ell_k,
+    const int* __restrict__ ell_col, const T* __restrict__ ell_val) {
+  extern __shared__ double lds[];
+  if (!ctl_runs(w.ctl, j)) return;
+  typedef T A4 __attribute__((ext_vector_type(4)));
+  const Grid gr = hw_grid();
+  const long long r0 = (long long)gr.bid * rows_per_block;
+  const long long r1 = min(n, r0 + rows_per_block);
+  // shared memory: the block's rows of z (rows_per_block values, a multiple
+  // of 256), then the reduction's own
+  T* zs = reinterpret_cast<T*>(lds);
+  double* sm = lds + (size_t)rows_per_block * sizeof(T) / sizeof(double);
+  const T* __restrict__ u = basis<T>(w) + (size_t)j * w.ldv;
+  T* __restrict__ zg = zvec<T>(w);
+  for (long long r = r0 + 4 * (long long)threadIdx.x; r < r1; r += 4LL * kReduceThreads) {
+    A4 o;
+    T out[4];
+    ell_rows4<T>(ell_col, ell_val, n, ell_k, u, r, out);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = out[i];
+    *reinterpret_cast<A4*>(zs + (r - r0)) = o;
+    __builtin_nontemporal_store(o, reinterpret_cast<A4*>(zg + r));   // see st16
+  }
+  __syncthreads();
+  reduce_body<CPW, true, true, T, true>(gr, w, n, j, rows_per_block, cpw, wc, wr, nullptr, 0,
+                                        nullptr, nullptr, sm, zs);
+}
+
+template <typename T>
+using OpReduceKernel = void (*)(Work, long long, int, long long, int, int, int, int, const int*,
+                                const T*);
+
+template <typename T>
+static OpReduceKernel<T> pick_opreduce(int tcpw) {
+  switch (tcpw) {
+    case 1: return opreduce_kernel<1, T>;
+    case 2: return opreduce_kernel<2, T>;
+    case 4: return opreduce_kernel<4, T>;
+    case 8: return opreduce_kernel<8, T>;
+    default: return nullptr;
+  }
+}
+
+// Largest share of a block's rows of z kept in shared memory (bytes).
+constexpr size_t kFusedZBytes = 128 * 1024;
+
+// The launch of the fused kernel for iteration j, or nblocks = 0 when the
+// operator apply and the reduction must run as two kernels: no ELL form,
+// n not a multiple of 4, arrays the vector loads cannot take, or a block's
+// rows of z beyond the shared memory.  The grid is the separate reduction's,
+// and the fused kernel must hold all of it resident at once.
+struct FusedLaunch {
+  const void* kernel = nullptr;
+  ReduceShape sh{};
+  size_t lds = 0;
+  int nblocks = 0;
+};
+
+template <typename T>
+static FusedLaunch opreduce_plan(const Op& op, const Work& w, long long n, int j) {
+  FusedLaunch f;
+  const T* ev = ell_vals<T>(op);
+  const T* V = basis<T>(w);
+  const T* z = zvec<T>(w);
+  if (op.dense || op.ell_k <= 0 || op.rpg != 0 || ev == nullptr || n % 4 != 0) return f;
+  if (reinterpret_cast<uintptr_t>(op.ell_col) % 16 != 0 ||
+      reinterpret_cast<uintptr_t>(ev) % (4 * sizeof(T)) != 0 ||
+      reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T)) != 0 ||
+      reinterpret_cast<uintptr_t>(V) % 16 != 0 || w.ldv % Vec16<T>::W != 0)
+    return f;
+  const int ncol = j + 1;
+  ReduceShape sh = reduce_columns(ncol);
+  const size_t red_lds = reduce_lds_bytes(sh, ncol);
+  // the separate reduction's grid (reduce_dispatch)
+  int cap = resident_blocks(reinterpret_cast<const void*>(pick_reduce<T>(sh.tcpw, true, true)),
+                            kReduceThreads, red_lds);
+  if (cap > kMaxBlocks) cap = kMaxBlocks;
+  if (sh.tcpw <= 2) {
+    const int cus = resident_blocks(nullptr, 0, 0);
+    if (cap > cus) cap = cus;
+  }
+  if (w.tune && (w.tune[j] & 1) && cap > 1) cap /= 2;
+  reduce_rows(sh, n, cap);
+  const size_t zbytes = (size_t)sh.rows_per_block * sizeof(T);
+  if (zbytes > kFusedZBytes) return f;
+  const void* k = reinterpret_cast<const void*>(pick_opreduce<T>(sh.tcpw));
+  if (k == nullptr) return f;
+  const size_t lds = zbytes + red_lds;
+  if (resident_blocks(k, kReduceThreads, lds) < sh.nblocks) return f;
+  f.kernel = k;
+  f.sh = sh;
+  f.lds = lds;
+  f.nblocks = sh.nblocks;
+  return f;
+}
+
+bool opreduce_fits(const Op& op, const Work& w, long long n, int j) {
+  return (w.fp32 ? opreduce_plan<float>(op, w, n, j) : opreduce_plan<double>(op, w, n, j))
+             .nblocks > 0;
+}
+
+template <typename T>
+static hipError_t opreduce_launch(const Op& op, const Work& w, long long n, int j, hipStream_t s,
+                                  int* nblocks_out) {
+  const FusedLaunch f = opreduce_plan<T>(op, w, n, j);
+  if (f.nblocks == 0) return hipErrorInvalidValue;
+  if (nblocks_out) *nblocks_out = f.nblocks;
+  Work wa = w;
+  long long na = n, rpb = f.sh.rows_per_block;
+  int ja = j, cpw = f.sh.cpw, wc = f.sh.wc, wr = f.sh.wr, k = op.ell_k;
+  const int* col = op.ell_col;
+  const T* val = ell_vals<T>(op);
+  void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &k, &col, &val};
+  return hipLaunchKernel(f.kernel, dim3(f.nblocks), dim3(kReduceThreads), args, f.lds, s);
+}
+
+hipError_t launch_opreduce(const Op& op, const Work& w, long long n, int j, hipStream_t s,
+                           int* nblocks_out) {
+  if (w.fp32) return opreduce_launch<float>(op, w, n, j, s, nblocks_out);
+  return opreduce_launch<double>(op, w, n, j, s, nblocks_out);
 }
 
 // ---------------------------------------------------------------------------

@@ -66,6 +66,7 @@ struct CycleKey {
   int m, gs, final_v, fp32;
   int lpr, dense;
   int rpg, tune_gen;
+  int fuse, pad;
 };
 
 }  // namespace
@@ -172,6 +173,78 @@ void free_raw(igs_ctx* c) {
   c->raw_part = c->raw_gpart = c->raw_out = c->raw_t = c->raw_r1 = nullptr;
   c->raw_tickets = nullptr;
   c->raw_cols = 0;
+}
+
+// Largest singular value of the first cycle's (J+1) x J Hessenberg matrix
+// (column-major, leading dimension ldh): Lanczos with full
+// reorthogonalisation on H^T H (at most 100 steps, exact when J <= 100),
+// then the largest eigenvalue of the Lanczos tridiagonal by bisection on its
+// Sturm sequence.  With an orthonormal basis, A V_J = V_{J+1} H, so the
+// result is ||A V_J||_2, a lower bound of ||A||_2 from the Krylov space the
+// solve built.  A diagnostic for the caller; no step of the solve uses it.
+double hessenberg_norm2(const std::vector<double>& H, int ldh, int J) {
+  if (J <= 0) return NAN;
+  const int kmax = std::min(J, 100);
+  std::vector<double> Q((size_t)kmax * J), w((size_t)J), hv((size_t)J + 1);
+  std::vector<double> al(kmax), be(kmax);
+  auto apply = [&](const double* v, double* out) {   // out = H^T (H v)
+    for (int i = 0; i <= J; ++i) hv[i] = 0.0;
+    for (int k = 0; k < J; ++k)
+      for (int i = 0; i <= k + 1 && i <= J; ++i) hv[i] += H[(size_t)k * ldh + i] * v[k];
+    for (int k = 0; k < J; ++k) {
+      double acc = 0.0;
+      for (int i = 0; i <= k + 1 && i <= J; ++i) acc += H[(size_t)k * ldh + i] * hv[i];
+      out[k] = acc;
+    }
+  };
+  for (int i = 0; i < J; ++i) Q[i] = 1.0 / sqrt((double)J);
+  int k = 0;
+  for (; k < kmax; ++k) {
+    const double* q = &Q[(size_t)k * J];
+    apply(q, w.data());
+    double a = 0.0;
+    for (int i = 0; i < J; ++i) a += q[i] * w[i];
+    al[k] = a;
+    // full reorthogonalisation against every Lanczos vector, twice
+    for (int pass = 0; pass < 2; ++pass)
+      for (int l = 0; l <= k; ++l) {
+        const double* ql = &Q[(size_t)l * J];
+        double d = 0.0;
+        for (int i = 0; i < J; ++i) d += ql[i] * w[i];
+        for (int i = 0; i < J; ++i) w[i] -= d * ql[i];
+      }
+    double b = 0.0;
+    for (int i = 0; i < J; ++i) b += w[i] * w[i];
+    b = sqrt(b);
+    be[k] = b;
+    if (k + 1 == kmax || !(b > 1e-14 * fabs(a))) { ++k; break; }
+    double* qn = &Q[(size_t)(k + 1) * J];
+    for (int i = 0; i < J; ++i) qn[i] = w[i] / b;
+  }
+  // largest eigenvalue of the k x k tridiagonal (al, be): bisection with
+  // Sturm counts on the Gershgorin interval
+  double lo = 0.0, hi = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < k ? fabs(be[i]) : 0.0);
+    hi = std::max(hi, al[i] + r);
+    lo = std::min(lo, al[i] - r);
+  }
+  auto below = [&](double x) {   // eigenvalues < x
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+      const double off = i > 0 ? be[i - 1] * be[i - 1] : 0.0;
+      d = al[i] - x - (i > 0 ? off / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(fabs(hi), 1e-300); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) < k) lo = mid; else hi = mid;
+  }
+  return sqrt(std::max(0.0, 0.5 * (lo + hi)));
 }
 
 long long pick_ldv(long long n) {
@@ -316,6 +389,7 @@ struct Timed {
 bool launch_ran(int kernel, int j, int j_end, int m) {
   switch (kernel) {
     case IGS_K_SPMV: return j <= j_end && j < m;
+    case IGS_K_OPREDUCE: return j <= j_end && j < m;
     case IGS_K_REDUCE: return j <= j_end;
     case IGS_K_UPDATE: return j <= j_end;
     default: return true;
@@ -628,6 +702,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   const int pmask = prof ? (o.profile_kernels ? o.profile_kernels : (1 << IGS_K_COUNT) - 1) : 0;
   const int final_v = o.final_basis_vector ? 1 : 0;
   const bool fp32 = o.inner_fp32 != 0;
+  const bool fuse = o.separate_apply == 0;
   // two-reduce with two sweeps: the one-sweep step plus a second reduction
   // and correction per iteration
   const bool two_reduce = o.two_reduce != 0 && gs_iters == 2;
@@ -705,7 +780,10 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     }
     const int jmax = check ? 0 : m;
     for (int j = 0; j <= jmax; ++j) {
-      if (j < m) {
+      // the operator apply inside the reduction's blocks where it fits,
+      // else as a kernel of its own before it (the same results either way)
+      const bool fused = fuse && j < m && igs::opreduce_fits(c->op, w, n, j);
+      if (j < m && !fused) {
         Timed tm(c, pmask, IGS_K_SPMV, j, cycles_timed, op_bytes);
         if (fp32)
           HIP_OR_FAIL(c, igs::launch_spmv32(c->op, w.V32 + (size_t)j * w.ldv, w.z32, w.ctl, j, st));
@@ -713,7 +791,12 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
           HIP_OR_FAIL(c, igs::launch_spmv(c->op, w.V + (size_t)j * w.ldv, w.z, w.ctl, j, st));
       }
       int nb = 0;
-      {
+      if (fused) {
+        // the operator's arrays and z written once; u read once, as column j
+        Timed tm(c, pmask, IGS_K_OPREDUCE, j, cycles_timed,
+                 op_bytes - es * dn + es * dn * (j + 1));
+        HIP_OR_FAIL(c, igs::launch_opreduce(c->op, w, n, j, st, &nb));
+      } else {
         Timed tm(c, pmask, IGS_K_REDUCE, j, cycles_timed,
                  es * dn * (j + 1) + (j < m ? es * dn : 0.0));
         HIP_OR_FAIL(c, igs::launch_reduce(w, n, j, j < m, st, &nb));
@@ -764,6 +847,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   key.tau = tau;
   key.cycle_rtol = cycle_rtol;
   key.maxit = maxit;
+  key.fuse = fuse ? 1 : 0;
   while (true) {
     const long long its_before = its;
     const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
@@ -872,6 +956,13 @@ extern "C" int igs_debug_copy_H(igs_ctx* c, double* H_host, int ldh, int* ncols)
     for (int i = 0; i <= J; ++i)
       H_host[(size_t)col * ldh + i] = (i <= col + 1) ? c->H_first[(size_t)col * c->ldh_first + i] : 0.0;
   *ncols = J;
+  return IGS_OK;
+}
+
+extern "C" int igs_anorm_estimate(igs_ctx* c, double* out) {
+  if (!c || !out) return IGS_EINVAL;
+  if (c->J_first <= 0) return set_err(c, IGS_EINVAL, "no finished column in a first cycle");
+  *out = hessenberg_norm2(c->H_first, c->ldh_first, c->J_first);
   return IGS_OK;
 }
 
@@ -1011,7 +1102,7 @@ extern "C" int igs_tune(igs_ctx* c, int restart, int gs_iters, igs_tune_report* 
     }
   }
   std::vector<double> red(m + 1), upd(m + 1);
-  double spmv_ms = 0.0, total_ms = 0.0;
+  double total_ms = 0.0;
   // two full cycles (tol 0) with every launch timed; per-iteration totals
   auto measure = [&]() -> int {
     igs_profile_reset(c);
@@ -1025,9 +1116,8 @@ extern "C" int igs_tune(igs_ctx* c, int restart, int gs_iters, igs_tune_report* 
     harvest(c, true);
     total_ms = 0.0;
     for (int k = 0; k < IGS_K_COUNT; ++k) total_ms += c->stats[k].ms;
-    spmv_ms = c->stats[IGS_K_SPMV].ms;
     for (int j = 0; j <= m; ++j) {
-      red[j] = c->stats_j[IGS_K_REDUCE][j].ms;
+      red[j] = c->stats_j[IGS_K_REDUCE][j].ms + c->stats_j[IGS_K_OPREDUCE][j].ms;
       upd[j] = c->stats_j[IGS_K_UPDATE][j].ms;
     }
     return IGS_OK;
@@ -1060,18 +1150,20 @@ extern "C" int igs_tune(igs_ctx* c, int restart, int gs_iters, igs_tune_report* 
     const int lpr = c->op.lpr;
     const int cands[3] = {1, 2, 4};
     const int maxr = lpr <= 8 ? 4 : (lpr == 16 ? 2 : 1);
+    // (compared on whole cycles: the default shape may run inside the
+    // reduction's blocks, the others as a kernel of their own)
     c->op.rpg = 0;
     c->tune_gen += 1;
     rc = measure();
-    double best = spmv_ms;
+    double best = total_ms;
     for (int q = 0; q < 3 && rc == IGS_OK; ++q) {
       const int r = cands[q];
       if (r > maxr || r == (lpr <= 8 ? 4 : (lpr == 16 ? 2 : 1))) continue;   // the default
       c->op.rpg = r;
       c->tune_gen += 1;
       rc = measure();
-      if (rc == IGS_OK && spmv_ms < 0.97 * best) {
-        best = spmv_ms;
+      if (rc == IGS_OK && total_ms < 0.97 * best) {
+        best = total_ms;
         best_rpg = r;
       }
     }

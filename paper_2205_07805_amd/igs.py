@@ -19,8 +19,9 @@ IGS_MAX_RESTART = 512
 IGS_MAX_BATCH = 32
 IGS_NOALLOC_MAX_COLS = 256
 IGS_NOALLOC_BYTES = (2048 + 64) * 2 * IGS_NOALLOC_MAX_COLS * 8 + 512
-(IGS_K_SPMV, IGS_K_REDUCE, IGS_K_UPDATE, IGS_K_XUPDATE, IGS_K_RESIDUAL, IGS_K_COUNT) = range(6)
-KERNEL_NAMES = ("spmv", "reduce", "update", "xupdate", "residual")
+(IGS_K_SPMV, IGS_K_REDUCE, IGS_K_UPDATE, IGS_K_XUPDATE, IGS_K_RESIDUAL, IGS_K_OPREDUCE,
+ IGS_K_COUNT) = range(7)
+KERNEL_NAMES = ("spmv", "reduce", "update", "xupdate", "residual", "opreduce")
 CYCLE_STATUS = ("running", "converged_at_start", "arnoldi_converged", "full", "breakdown",
                 "lagnorm", "maxit", "nonfinite")
 
@@ -29,7 +30,7 @@ EXPORTED = (
     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
     "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
     "igs_serve", "igs_solve_batch", "igs_serve_batched", "igs_tune", "igs_tune_reset",
-    "igs_kernel_reduce_noalloc",
+    "igs_kernel_reduce_noalloc", "igs_anorm_estimate",
 )
 
 
@@ -37,7 +38,7 @@ class IgsOpts(ctypes.Structure):
     _fields_ = [("maxit", c_int64), ("lagnorm_tau", c_double), ("final_basis_vector", c_int),
                 ("profile", c_int), ("max_cycles", c_int), ("keep_first_basis", c_int),
                 ("profile_kernels", c_int), ("inner_fp32", c_int), ("two_reduce", c_int),
-                ("reserved", c_int * 1),
+                ("separate_apply", c_int),
                 ("inner_rtol", c_double), ("batch_reduce_rows", c_int),
                 ("batch_update_tiles", c_int), ("cycle_graph", c_int), ("mgs", c_int)]
 
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "igs_kernel_reduce": (c_int, [P, P, c_int64, c_int, P, P, P]),
         "igs_kernel_update": (c_int, [P, P, c_int64, c_int, P, P, P, c_double]),
         "igs_kernel_reduce_noalloc": (c_int, [P, c_int64, c_int64, c_int, P, P, P]),
+        "igs_anorm_estimate": (c_int, [P, POINTER(c_double)]),
         "igs_profile_get": (c_int, [P, c_int, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
         "igs_profile_reset": (c_int, [P]),
         "igs_serve": (c_int, [POINTER(IgsRequest), c_int, c_int, c_int64, c_int, c_double, c_int,
@@ -218,6 +220,12 @@ def igs_kernel_reduce_noalloc(V, ldv, n, j, z, PQ, hip_stream=None) -> None:
     None for the null stream) and returns without waiting."""
     _check("igs_kernel_reduce_noalloc", load_library().igs_kernel_reduce_noalloc(
         _ptr(V), int(ldv), int(n), int(j), _ptr(z), _ptr(PQ), _ptr(hip_stream)), None)
+
+
+def igs_anorm_estimate(ctx) -> float:
+    out = c_double(0.0)
+    _check("igs_anorm_estimate", load_library().igs_anorm_estimate(ctx, ctypes.byref(out)), ctx)
+    return out.value
 
 
 def igs_profile_get(ctx, which):

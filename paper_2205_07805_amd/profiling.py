@@ -64,7 +64,8 @@ def family(name: str) -> str | None:
     for key in ("spmv_csr_kernel", "spmv_ell_kernel", "gemv_dense_kernel"):
         if key in s:
             return "spmv"
-    for key, fam in (("reduce_kernel", "reduce"), ("update_kernel", "update"),
+    for key, fam in (("opreduce_kernel", "opreduce"), ("reduce_kernel", "reduce"),
+                     ("update_kernel", "update"),
                      ("xupdate_kernel", "xupdate"), ("lsq_kernel", "lsq"),
                      ("cycle_begin_kernel", "cycle_begin"), ("bnorm_kernel", "bnorm")):
         if key in s:
@@ -110,9 +111,9 @@ def label_launches(rows):
                 continue
             out.append((solve, "spmv", j + 1, cycle))
             continue
-        if fam == "reduce":
+        if fam in ("reduce", "opreduce"):
             j += 1
-            out.append((solve, "reduce", j, cycle))
+            out.append((solve, fam, j, cycle))
             continue
         out.append((solve, fam, j if fam == "update" else None, cycle))
     return out
@@ -130,13 +131,15 @@ def trace_summary(trace_csv: str, solves=None) -> str:
     # operator apply of that iteration was gated off too
     idle = set()
     for r, l in zip(rows, labels):
-        if l and l[1] == "reduce" and (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 < NOOP_US:
+        if l and l[1] in ("reduce", "opreduce") and \
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 < NOOP_US:
             idle.add((l[3], l[2]))
     for r, l in zip(rows, labels):
         if l is None or not (lo <= l[0] < hi):
             continue
         us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-        if (l[1] in ("reduce", "update") and us < NOOP_US) or (l[1] == "spmv" and (l[3], l[2]) in idle):
+        if (l[1] in ("reduce", "opreduce", "update") and us < NOOP_US) or \
+                (l[1] == "spmv" and (l[3], l[2]) in idle):
             noop[l[1]] += 1
             continue
         per[l[1]].append(us)
@@ -150,13 +153,14 @@ def trace_summary(trace_csv: str, solves=None) -> str:
     for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"{k:12s} {len(v):8d} {sum(v) / len(v):9.2f} {sum(v) / 1e3:9.2f}"
                      f"  ({100 * sum(v) / tot:4.1f}%)")
-    lines += ["", "per iteration j (average us): reduce  update  spmv"]
+    lines += ["", "per iteration j (average us): opreduce  reduce  update  spmv"]
     js = sorted({j for (_, j) in perj})
     for j in js:
         if j % 5 and j != js[-1]:
             continue
         f = lambda k: (sum(perj[(k, j)]) / len(perj[(k, j)])) if perj.get((k, j)) else float("nan")
-        lines.append(f"  j={j:3d} {f('reduce'):8.2f} {f('update'):8.2f} {f('spmv'):8.2f}")
+        lines.append(f"  j={j:3d} {f('opreduce'):8.2f} {f('reduce'):8.2f} {f('update'):8.2f} "
+                     f"{f('spmv'):8.2f}")
     return "\n".join(lines)
 
 
@@ -177,6 +181,9 @@ def _calibration(rows):
 
 
 def algorithmic_bytes(fam, j, n, nnz, m):
+    if fam == "opreduce":
+        # the operator's arrays, z written once, V_{0:j} and u read once
+        return 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n + 8.0 * n * (j + 1)
     if fam == "reduce":
         return 8.0 * n * (j + 1) + (8.0 * n if j < m else 0.0)
     if fam == "update":
@@ -195,7 +202,7 @@ def traffic(fetch_csv, write_csv, n, nnz, m, workload, solve=0, copy_bytes=256 *
     for rows, key in ((f_rows, "fetch"), (w_rows, "write")):
         seq = collections.defaultdict(list)
         for r, l in zip(rows, label_launches(rows)):
-            if l is None or l[0] != solve or l[1] not in ("spmv", "reduce", "update"):
+            if l is None or l[0] != solve or l[1] not in ("spmv", "opreduce", "reduce", "update"):
                 continue
             seq[(l[1], l[2])].append(float(r["Counter_Value"]) * 1024.0 * (sf if key == "fetch" else sw))
         fam_launch[key] = seq
@@ -204,7 +211,7 @@ def traffic(fetch_csv, write_csv, n, nnz, m, workload, solve=0, copy_bytes=256 *
                            "FETCH_SIZE_KiB": cf, "WRITE_SIZE_KiB": cw,
                            "fetch_scale": sf, "write_scale": sw},
            "kernels": {}}
-    for fam in ("spmv", "reduce", "update"):
+    for fam in ("spmv", "opreduce", "reduce", "update"):
         fetch = write = alg = 0.0
         cnt = 0
         for (fm, j), fv in fam_launch["fetch"].items():

@@ -352,3 +352,28 @@ def test_two_reduce_gs2_convdiff3d_ragged(torch):
     ref = O.gmres(a, b, restart=30, tol=1e-10, variant="igs2r", gs_iters=2)
     assert rc == 0 and abs(info["iters"] - ref.iters) <= 2
     assert_H_close(H, ref.first_cycle.H)
+
+
+def test_anorm_estimate(torch):
+    """igs_anorm_estimate: the largest singular value of the first cycle's
+    Hessenberg matrix (||A V_J||_2), equal to numpy's 2-norm of the H the
+    solve returns, at most the exact ||A||_2, and close to it here."""
+    import scipy.sparse as sp
+    from paper_2205_07805_amd import Solver, igs
+    a = W.convdiff2d(32, 10.0)
+    b = W.rhs_normal(a.n, 0)
+    print("anorm estimate", flush=True)
+    A = sp.csr_matrix((a.vals, a.col_idx, a.row_ptr), shape=(a.n, a.n)).toarray()
+    exact = np.linalg.norm(A, 2)
+    for restart in (50, 150):    # Lanczos exact (J <= 100) and truncated at 100 steps
+        s = Solver(a)
+        try:
+            x, rc, info = s.solve(b, restart=restart, tol=1e-12, gs_iters=2)
+            H = s.first_cycle_H()
+            est = igs.igs_anorm_estimate(s.ctx)
+        finally:
+            s.close()
+        sig = np.linalg.norm(H, 2)
+        assert abs(est - sig) <= 1e-10 * sig, (restart, est, sig)
+        assert est <= exact * (1 + 1e-12)
+        assert est >= 0.99 * exact, (est, exact)
