@@ -132,6 +132,14 @@ typedef struct igs_opts {
                            not apply; not with inner_fp32 or two_reduce
                            (IGS_ENOTIMPL); profile and cycle_graph are
                            ignored.                                           */
+  int products_in_update; /* 1: every block of the update kernel forms the
+                             small products with T and H itself also when
+                             they no longer fit its shared memory (large
+                             restart lengths).  By default a kernel of their
+                             own forms them first, one wave per output over
+                             many CUs (Section 4's operation counts: the
+                             triangular work grows as j^2); the results are
+                             bit-identical either way.                     */
 } igs_opts;
 
 /* Result summary of a solve.  Any pointer argument of this type may be NULL. */
@@ -356,6 +364,16 @@ int igs_debug_copy_V(igs_ctx *ctx, double *V_dev, int64_t ldv, int *ncols);
  * an upper bound.  Not part of the solve's time.  Errors: IGS_EINVAL when the
  * first cycle finished no column. */
 int igs_anorm_estimate(igs_ctx *ctx, double *anorm_out);
+
+/* Kernel of the dense operator apply z = A u (Section 1's real n x n A):
+ *   IGS_DENSE_VALU: one wavefront per row, 16-byte loads, a wave sum;
+ *   IGS_DENSE_MFMA: the matrix cores (v_mfma_f64_16x16x4f64), a block per 16
+ *                   rows, the vector as the A operand of each product.
+ * Both are bound by the matrix's bytes; the default is the faster one on
+ * MI355X (IGS_DENSE_DEFAULT).  Errors: IGS_EINVAL (not a dense context, or
+ * an unknown variant). */
+enum { IGS_DENSE_VALU = 0, IGS_DENSE_MFMA = 1 };
+int igs_dense_variant(igs_ctx *ctx, int variant);
 
 /* ---- Step kernels on caller buffers (unit tests of each hot-path step) --- */
 

@@ -72,8 +72,9 @@ struct Op {
   const int* row_ptr;
   const int* col_idx;
   const double* vals;
-  const double* A;     // dense
+  const double* A;     // dense (columns n..lda-1 of every row hold zeros)
   long long lda;
+  int dense_mfma;      // dense: 1 = the matrix-core kernel, 0 = one wave per row
   int lpr;             // CSR lanes per row
   const float* vals32; // CSR values rounded to FP32 (mixed precision; may be null)
   int rpg;             // CSR rows per lane group (0: the default for lpr; set by the tuner)
@@ -110,6 +111,11 @@ struct Work {
   // iteration j, bit 0 halves the blocks of the fused reduction and bit 1
   // those of the update (each block then takes twice the rows).
   const unsigned char* tune;
+  // The small products of an iteration whose T and H do not fit the update
+  // kernel's shared memory, formed beforehand by coef_kernel (3 (m + 2)
+  // doubles); pre_on = 0: every update block forms them itself.
+  double* pre;
+  int pre_on;
 };
 
 // Groups of the first level of the deterministic grid reduction for a grid
@@ -143,6 +149,12 @@ hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStre
 bool opreduce_fits(const Op& op, const Work& w, long long n, int j);
 hipError_t launch_opreduce(const Op& op, const Work& w, long long n, int j, hipStream_t s,
                            int* nblocks_out);
+// Whether iteration j's small products run in a kernel of their own before
+// the update (w.pre_on, and T and H beyond the update's shared memory).
+bool coef_kernel_needed(const Work& w, int j);
+// That kernel: t = T p (or T q / gamma with one sweep), H (t_prev / gamma_prev)
+// and the new row of T, one wave per output.
+hipError_t launch_coef(const Work& w, int j, int ngroups, hipStream_t s);
 // ngroups: the group totals the reduction of iteration j left in w.gpart.
 hipError_t launch_update(const Work& w, long long n, int j, int gs, int ngroups, hipStream_t s);
 // Second Gauss-Seidel sweep of the two-reduce variant for the vector in

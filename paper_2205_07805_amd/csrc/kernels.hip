@@ -384,6 +384,75 @@ __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const doub
   if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
 }
 
+// Dense row-major operator on the matrix cores (v_mfma_f64_16x16x4f64).  A
+// block owns 16 rows; its 8 waves take interleaved steps of 32 columns.  In
+// a step, lane l (r = l % 16, q = l / 16) reads the 8 entries of row
+// i0 + r at columns kb + 8q .. kb + 8q + 7 (four 16-byte loads, so the wave
+// reads 256 contiguous bytes of each of its 16 rows) and x at the same
+// columns.  Eight MFMAs then take, for t = 0..7, the vector as the A operand
+// (A[i][kk] = x[kb + 8kk + t], the same in every row i) and the matrix as the
+// B operand (B[kk][j] = A[i0 + j][kb + 8kk + t]), so that every row i of the
+// 16 x 16 accumulator holds the partial products of rows i0 .. i0 + 15 in its
+// columns j: column j of the result is held by the lanes with l % 16 = j, in
+// all four of their accumulator values.  The single right-hand side uses one
+// of the 16 accumulator rows' worth of work; the kernel is bound by the
+// matrix's bytes, not by the matrix cores.  The 8 waves' partial sums are
+// added in a fixed order in shared memory.  Needs lda a multiple of 32 with
+// zeros in columns n .. lda - 1 (igs_create_dense pads that way).
+constexpr int kGemvWaves = 8;
+__global__ __launch_bounds__(kGemvWaves * 64) void gemv_mfma_kernel(
+    long long n, const double* __restrict__ A, long long lda, const double* __restrict__ x,
+    double* __restrict__ y, const double* __restrict__ bsub, const Ctl* __restrict__ gate,
+    int gate_j) {
+  __shared__ double part[kGemvWaves][16];
+  if (gate != nullptr && !ctl_runs(gate, gate_j)) return;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int r = lane % 16, q = lane / 16;
+  const long long i0 = (long long)blockIdx.x * 16;
+  // rows past the end read the last row; their sums are not stored
+  const long long row = min(i0 + r, n - 1);
+  const double* __restrict__ arow = A + row * lda;
+  const long long nsteps = (n + 31) / 32;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  // two steps per round, every load of both issued before the products
+  auto load = [&](long long st, double* a, double* xv) {
+    const long long kb = st * 32 + 8 * q;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const dvec2 av = ld_stream2(arow + kb + 2 * h);
+      a[2 * h] = av[0];
+      a[2 * h + 1] = av[1];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xv[t] = (kb + t < n) ? x[kb + t] : 0.0;
+  };
+  for (long long st = wave; st < nsteps; st += 2 * kGemvWaves) {
+    const bool two = st + kGemvWaves < nsteps;   // the same for the whole wave
+    double a0[8], x0[8], a1[8], x1[8];
+    load(st, a0, x0);
+    load(two ? st + kGemvWaves : st, a1, x1);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t], a0[t], acc, 0, 0, 0);
+    if (two) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t], a1[t], acc, 0, 0, 0);
+    }
+  }
+  // column r of the accumulator: row i0 + r, the same in every entry
+  if (q == 0) part[wave][r] = acc[0];
+  __syncthreads();
+  if (threadIdx.x < 16 && i0 + threadIdx.x < n) {
+    double s = part[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kGemvWaves; ++w) s += part[w][threadIdx.x];
+    const long long i = i0 + threadIdx.x;
+    y[i] = (bsub != nullptr) ? bsub[i] - s : s;
+  }
+}
+
 // The operator apply from the ELL form, RPT rows per thread: the same
 // products and the same order of additions as the CSR kernel with 8 lanes
 // per row (pairs, then quads, then the two halves; entries past the row's
@@ -458,6 +527,13 @@ static hipError_t op_apply(const Op& op, const TA* x, TY* y, const TA* bsub, con
                            int gate_j, hipStream_t s) {
   if (op.dense) {
     if constexpr (std::is_same<TA, double>::value && std::is_same<TY, double>::value) {
+      if (op.dense_mfma) {
+        if (op.lda % 32 != 0) return hipErrorInvalidValue;
+        const unsigned grid = (unsigned)((op.n + 15) / 16);
+        hipLaunchKernelGGL(gemv_mfma_kernel, dim3(grid), dim3(kGemvWaves * 64), 0, s, op.n, op.A,
+                           op.lda, x, y, bsub, gate, gate_j);
+        return hipGetLastError();
+      }
       const int rows_per_block = 4;
       const unsigned grid = (unsigned)((op.n + rows_per_block - 1) / rows_per_block);
       hipLaunchKernelGGL(gemv_dense_kernel, dim3(grid), dim3(256), 0, s, op.n, op.A, op.lda, x, y,
@@ -890,9 +966,20 @@ struct StepCoefs {
   double ig;  // 1 / gamma
 };
 
-template <bool STAGED>
+// Where the products with T and H come from: computed by the block from
+// global memory, from the staged copies in shared memory, or read as
+// coef_kernel left them (PRE: iterations beyond the staging limit).
+enum SolveKind : int { kSolveGlobal = 0, kSolveStaged = 1, kSolvePre = 2 };
+
+// Offsets of the products coef_kernel forms for iteration j in w.pre.
+__host__ __device__ __forceinline__ int pre_t(int j) { return 0; }
+__host__ __device__ __forceinline__ int pre_h(int j) { return j + 2; }
+__host__ __device__ __forceinline__ int pre_row(int j) { return 2 * (j + 2); }
+
+template <int KIND>
 __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, const double* P,
                                  const double* Q, double* sm, bool pub) {
+  constexpr bool STAGED = (KIND == kSolveStaged);
   Ctl* ctl = w.ctl;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
@@ -991,7 +1078,11 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
 
   // ---- second sweep t = (I + L_{0:j,0:j})^{-1} p = T_j p  (gs = 2), and p.p
   if (gs == 2) {
-    tri_matvec<STAGED>(Ts, P, st, j);
+    if constexpr (KIND == kSolvePre) {
+      for (int i = tid; i < j; i += blockDim.x) st[i] = w.pre[pre_t(j) + i];
+    } else {
+      tri_matvec<STAGED>(Ts, P, st, j);
+    }
   } else {
     for (int i = tid; i < j; i += blockDim.x) st[i] = 0.0;
   }
@@ -1007,7 +1098,11 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
 
   // ---- finished column j-1 (publisher): r1_prev + t - H[0:j, 0:j-1] (t_prev / gamma_prev)
   if (pub && gs == 2) {
-    hess_matvec<STAGED>(Hs, sx, sr1, j);   // sr1 is free until the first sweep below
+    if constexpr (KIND == kSolvePre) {
+      for (int i = tid; i < j; i += blockDim.x) sr1[i] = w.pre[pre_h(j) + i];
+    } else {
+      hess_matvec<STAGED>(Hs, sx, sr1, j);   // sr1 is free until the first sweep below
+    }
     __syncthreads();
     for (int i = tid; i < j; i += blockDim.x) shc[i] = shc[i] + st[i] - sr1[i];
   }
@@ -1062,7 +1157,11 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
   if (pub) {
     const int brk = finish_column(w, j, shc, gamma, scs, ssn, s_gc, n);   // synchronises
     if (!brk) {
-      tri_rowvec<STAGED>(Ts, sl, sx, j);
+      if constexpr (KIND == kSolvePre) {
+        for (int c = tid; c < j; c += blockDim.x) sx[c] = w.pre[pre_row(j) + c];
+      } else {
+        tri_rowvec<STAGED>(Ts, sl, sx, j);
+      }
       __syncthreads();
       double* trow = w.T + tri_row(j);
       for (int c = tid; c < j; c += blockDim.x) trow[c] = sx[c];
@@ -1101,9 +1200,13 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
       }
     } else {
       // r1 = (I + L_{0:j+1,0:j+1})^{-1} [q/gamma ; beta/gamma^2]
-      for (int c = tid; c < j; c += blockDim.x) sx[c] = Q[c] * ig;
-      __syncthreads();
-      tri_matvec<STAGED>(Ts, sx, sr1, j);
+      if constexpr (KIND == kSolvePre) {
+        for (int c = tid; c < j; c += blockDim.x) sr1[c] = w.pre[pre_t(j) + c];
+      } else {
+        for (int c = tid; c < j; c += blockDim.x) sx[c] = Q[c] * ig;
+        __syncthreads();
+        tri_matvec<STAGED>(Ts, sx, sr1, j);
+      }
       __syncthreads();
       if (wave == 0) {
         const double d = wave_dot(sl, sr1, j);
@@ -1127,6 +1230,112 @@ __device__ StepCoefs small_solve(const Work& w, long long n, int j, bool tail, c
   }
   out.mode = run_mode;
   return out;
+}
+
+// ---------------------------------------------------------------------------
+// The small products of a large iteration, spread over many CUs
+// ---------------------------------------------------------------------------
+//
+// Past the staging limit every update block would read the prefixes of T and
+// H from global memory one row per wave, a memory latency per row, and the
+// publishing block three such products in a row (about 100 us at j = 195).
+// This kernel forms them once, one wave per output over as many blocks as
+// there are outputs, before the update; the update blocks then read j values
+// of each.  Each output is the update's own unstaged product (lanes stride the
+// row, then a wave sum) on the same reduction totals summed in the same order,
+// so the values are bit-identical to the ones the update blocks would form:
+//   pre_t:   gs = 2: t = T_j p;  gs = 1: T_j (q / gamma), the first sweep;
+//   pre_h:   gs = 2: H[0:j, 0:j-1] (t_prev / gamma_prev), for the finished column;
+//   pre_row: -(p / gamma)^T T_j, the new row of T (eq:block); skipped when the
+//            lagged norm cancels (the update then takes the fallback).
+__global__ __launch_bounds__(256) void coef_kernel(Work w, int j, int ngroups) {
+  extern __shared__ double lds[];
+  const Ctl* ctl = w.ctl;
+  if (!ctl_runs(ctl, j)) return;
+  double* P = lds;                 // V^T u, u^T u
+  double* Q = lds + (j + 1);       // V^T z, u^T z
+  double* X = lds + 2 * (j + 1);   // the vector each product multiplies
+  double* Lr = X + (j + 1);        // p / gamma
+  __shared__ double s_ig, s_pp;
+  __shared__ int s_ok;
+  for (int v = threadIdx.x; v < 2 * (j + 1); v += blockDim.x) {
+    double g8[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) g8[g] = (g < ngroups) ? w.gpart[(size_t)g * w.pstride + v] : 0.0;
+    double acc = g8[0];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) acc += g8[g];
+    lds[v] = acc;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int gs = ctl->gs;
+  const double alpha = P[j];
+  if (wave == 0) {
+    const double pp = wave_dot(P, P, j);
+    if (lane == 0) {
+      s_pp = pp;
+      int ok = 1;
+      double gamma;
+      if (gs == 2) {
+        const double g2 = alpha - pp;
+        if (!(g2 >= ctl->lagnorm_tau * alpha) || !(g2 > 0.0)) ok = 0;
+        gamma = ok ? sqrt(g2) : 1.0;
+      } else {
+        gamma = sqrt(alpha);
+      }
+      s_ig = 1.0 / gamma;
+      s_ok = ok;
+    }
+  }
+  __syncthreads();
+  const double ig = s_ig;
+  const double igp = 1.0 / ctl->gamma_prev;
+  for (int c = threadIdx.x; c < j; c += blockDim.x) {
+    X[c] = (gs == 2) ? w.coef_t[c] * igp : Q[c] * ig;   // t_prev / gamma_prev, or q / gamma
+    Lr[c] = P[c] * ig;
+  }
+  __syncthreads();
+  // outputs: [0, j) first products, [j, 2j) H products (gs = 2), [2j, 3j) the T row
+  const int o = blockIdx.x * (blockDim.x / kWave) + wave;
+  if (o < j) {
+    const int i = o;
+    const double* trow = w.T + tri_row(i);
+    const double* x = (gs == 2) ? P : X;
+    double acc = 0.0;
+    for (int c = lane; c <= i; c += kWave) acc = fma(trow[c], x[c], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) w.pre[pre_t(j) + i] = acc;
+  } else if (o < 2 * j) {
+    const int i = o - j;
+    if (gs == 2 && j >= 1) {
+      double acc = 0.0;
+      for (int c = (i > 0 ? i - 1 : 0) + lane; c < j - 1; c += kWave)
+        acc = fma(w.H[hess_col(c) + i], X[c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) w.pre[pre_h(j) + i] = acc;
+    }
+  } else if (o < 3 * j) {
+    const int c = o - 2 * j;
+    if (s_ok) {
+      double acc = 0.0;
+      for (int i = c + lane; i < j; i += kWave) acc = fma(Lr[i], w.T[tri_row(i) + c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) w.pre[pre_row(j) + c] = -acc;
+    }
+  }
+}
+
+bool coef_kernel_needed(const Work& w, int j) {
+  return w.pre_on && w.pre != nullptr && j >= 1 && stage_count(j) == 0;
+}
+
+hipError_t launch_coef(const Work& w, int j, int ngroups, hipStream_t s) {
+  const int outputs = 3 * j;
+  const unsigned grid = (unsigned)((outputs + 3) / 4);
+  const size_t lds = sizeof(double) * (size_t)4 * (j + 1);
+  hipLaunchKernelGGL(coef_kernel, dim3(grid), dim3(256), lds, s, w, j, ngroups);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1860,8 +2069,11 @@ __device__ __forceinline__ void update_body(
       ig = 1.0;
     } else {
       const bool tail = (j >= w.ctl->m);
-      const StepCoefs c = (stage_count(j) > 0) ? small_solve<true>(w, n, j, tail, sP, sQ, sm, pub)
-                                               : small_solve<false>(w, n, j, tail, sP, sQ, sm, pub);
+      const StepCoefs c =
+          (stage_count(j) > 0)
+              ? small_solve<kSolveStaged>(w, n, j, tail, sP, sQ, sm, pub)
+              : (w.pre_on ? small_solve<kSolvePre>(w, n, j, tail, sP, sQ, sm, pub)
+                          : small_solve<kSolveGlobal>(w, n, j, tail, sP, sQ, sm, pub));
       mode = c.mode;
       ig = c.ig;
       if (mode == kUpdNone) return;

@@ -66,7 +66,8 @@ struct CycleKey {
   int m, gs, final_v, fp32;
   int lpr, dense;
   int rpg, tune_gen;
-  int fuse, pad;
+  int dense_mfma, pad2;
+  int fuse, pre;
 };
 
 }  // namespace
@@ -132,6 +133,9 @@ struct igs_ctx {
 
 namespace {
 
+// The dense operator apply the contexts start with (igs_dense_variant changes it).
+constexpr int DENSE_MFMA_DEFAULT = 0;
+
 int set_err(igs_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -153,7 +157,7 @@ int set_err(igs_ctx* c, int code, const char* fmt, ...) {
 
 void free_workspace(igs_ctx* c) {
   Work& w = c->w;
-  void* ptrs[] = {w.V, w.z, w.H, w.R, w.T, w.L, w.cs, w.sn, w.g, w.y, w.coef_t, w.coef_r1,
+  void* ptrs[] = {w.V, w.z, w.H, w.R, w.T, w.L, w.cs, w.sn, w.g, w.y, w.coef_t, w.coef_r1, w.pre,
                   w.part, w.gpart, w.tickets, w.ctl, c->d_V_first, w.V32, w.z32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -275,6 +279,7 @@ int ensure_workspace(igs_ctx* c, int m) {
   HIP_OR_FAIL(c, dalloc(&w.y, (size_t)m));
   HIP_OR_FAIL(c, dalloc(&w.coef_t, (size_t)m + 2));
   HIP_OR_FAIL(c, dalloc(&w.coef_r1, (size_t)m + 2));
+  HIP_OR_FAIL(c, dalloc(&w.pre, (size_t)3 * (m + 2)));
   HIP_OR_FAIL(c, dalloc(&w.part, (size_t)igs::kMaxBlocks * w.pstride));
   HIP_OR_FAIL(c, dalloc(&w.gpart, (size_t)igs::kMaxGroups * w.pstride));
   HIP_OR_FAIL(c, dalloc(&w.tickets, (size_t)igs::kMaxGroups + 1));
@@ -606,6 +611,12 @@ extern "C" int igs_create_dense(igs_ctx** out, int64_t n, const double* A, int64
     set_err(c, IGS_ENOMEM, "device allocation of A failed");
     return fail_create(c, IGS_ENOMEM);
   }
+  // zeros in the padding columns: the matrix-core kernel reads whole steps
+  // of 32 columns
+  if (hipMemset(c->d_A, 0, sizeof(double) * n * ldd) != hipSuccess) {
+    set_err(c, IGS_EDEVICE, "clearing A on the device failed");
+    return fail_create(c, IGS_EDEVICE);
+  }
   if (hipMemcpy2D(c->d_A, ldd * sizeof(double), src, lda * sizeof(double), n * sizeof(double), n,
                   hipMemcpyHostToDevice) != hipSuccess) {
     set_err(c, IGS_EDEVICE, "copy of A to the device failed");
@@ -615,6 +626,7 @@ extern "C" int igs_create_dense(igs_ctx** out, int64_t n, const double* A, int64
   c->op.n = n;
   c->op.A = c->d_A;
   c->op.lda = ldd;
+  c->op.dense_mfma = DENSE_MFMA_DEFAULT;
   *out = c;
   return IGS_OK;
 }
@@ -720,6 +732,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   Work& w = c->w;
   w.fp32 = fp32 ? 1 : 0;
   w.tune = c->tune.empty() ? nullptr : c->tune.data();
+  // the small products of large iterations in a kernel of their own
+  w.pre_on = o.products_in_update ? 0 : 1;
   hipStream_t s = c->stream;
   c->J_first = -1;
   c->V_first_valid = 0;
@@ -805,6 +819,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       // The tail update (j = m) finishes the last column (and the lagged-norm
       // fallback there) and writes v_m on request; it never writes column
       // m + 1.
+      if (igs::coef_kernel_needed(w, j))
+        HIP_OR_FAIL(c, igs::launch_coef(w, j, igs::reduce_groups(nb), st));
       {
         Timed tm(c, pmask, IGS_K_UPDATE, j, cycles_timed, es * dn * (j + 1) + 3.0 * es * dn);
         HIP_OR_FAIL(c, igs::launch_update(w, n, j, gs_step, igs::reduce_groups(nb), st));
@@ -838,6 +854,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   key.lpr = c->op.lpr;
   key.dense = c->op.dense;
   key.rpg = c->op.rpg;
+  key.dense_mfma = c->op.dense_mfma;
   key.tune_gen = c->tune_gen;
   key.m = m;
   key.gs = gs_step;
@@ -848,6 +865,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   key.cycle_rtol = cycle_rtol;
   key.maxit = maxit;
   key.fuse = fuse ? 1 : 0;
+  key.pre = w.pre_on;
   while (true) {
     const long long its_before = its;
     const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
@@ -956,6 +974,15 @@ extern "C" int igs_debug_copy_H(igs_ctx* c, double* H_host, int ldh, int* ncols)
     for (int i = 0; i <= J; ++i)
       H_host[(size_t)col * ldh + i] = (i <= col + 1) ? c->H_first[(size_t)col * c->ldh_first + i] : 0.0;
   *ncols = J;
+  return IGS_OK;
+}
+
+extern "C" int igs_dense_variant(igs_ctx* c, int variant) {
+  if (!c) return IGS_EINVAL;
+  if (!c->op.dense) return set_err(c, IGS_EINVAL, "not a dense operator");
+  if (variant != IGS_DENSE_VALU && variant != IGS_DENSE_MFMA)
+    return set_err(c, IGS_EINVAL, "variant must be IGS_DENSE_VALU or IGS_DENSE_MFMA");
+  c->op.dense_mfma = (variant == IGS_DENSE_MFMA) ? 1 : 0;
   return IGS_OK;
 }
 
@@ -1523,6 +1550,7 @@ void batch_row(Batch& B, int k, const BatchParams& p) {
   igs::Inst& I = B.h_tab[k];
   I.w = M.c->w;
   I.w.fp32 = p.fp32;
+  I.w.pre_on = 0;   // batched updates form the small products themselves
   I.op = M.c->op;
   I.n = M.c->n;
   I.b = M.b;

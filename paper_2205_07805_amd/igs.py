@@ -30,7 +30,7 @@ EXPORTED = (
     "igs_last_error", "igs_debug_copy_H", "igs_debug_copy_V", "igs_kernel_spmv",
     "igs_kernel_reduce", "igs_kernel_update", "igs_profile_get", "igs_profile_reset",
     "igs_serve", "igs_solve_batch", "igs_serve_batched", "igs_tune", "igs_tune_reset",
-    "igs_kernel_reduce_noalloc", "igs_anorm_estimate",
+    "igs_kernel_reduce_noalloc", "igs_anorm_estimate", "igs_dense_variant",
 )
 
 
@@ -40,7 +40,8 @@ class IgsOpts(ctypes.Structure):
                 ("profile_kernels", c_int), ("inner_fp32", c_int), ("two_reduce", c_int),
                 ("separate_apply", c_int),
                 ("inner_rtol", c_double), ("batch_reduce_rows", c_int),
-                ("batch_update_tiles", c_int), ("cycle_graph", c_int), ("mgs", c_int)]
+                ("batch_update_tiles", c_int), ("cycle_graph", c_int), ("mgs", c_int),
+                ("products_in_update", c_int)]
 
 
 class IgsInfo(ctypes.Structure):
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "igs_kernel_update": (c_int, [P, P, c_int64, c_int, P, P, P, c_double]),
         "igs_kernel_reduce_noalloc": (c_int, [P, c_int64, c_int64, c_int, P, P, P]),
         "igs_anorm_estimate": (c_int, [P, POINTER(c_double)]),
+        "igs_dense_variant": (c_int, [P, c_int]),
         "igs_profile_get": (c_int, [P, c_int, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
         "igs_profile_reset": (c_int, [P]),
         "igs_serve": (c_int, [POINTER(IgsRequest), c_int, c_int, c_int64, c_int, c_double, c_int,
@@ -220,6 +222,13 @@ def igs_kernel_reduce_noalloc(V, ldv, n, j, z, PQ, hip_stream=None) -> None:
     None for the null stream) and returns without waiting."""
     _check("igs_kernel_reduce_noalloc", load_library().igs_kernel_reduce_noalloc(
         _ptr(V), int(ldv), int(n), int(j), _ptr(z), _ptr(PQ), _ptr(hip_stream)), None)
+
+
+IGS_DENSE_VALU, IGS_DENSE_MFMA = 0, 1
+
+
+def igs_dense_variant(ctx, variant) -> None:
+    _check("igs_dense_variant", load_library().igs_dense_variant(ctx, int(variant)), ctx)
 
 
 def igs_anorm_estimate(ctx) -> float:

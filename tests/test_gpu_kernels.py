@@ -66,19 +66,40 @@ def test_spmv_csr_matches_oracle(torch, case):
         igs.igs_destroy(ctx)
 
 
-@pytest.mark.parametrize("n", [1, 63, 1000, 1001])
-def test_gemv_dense_matches_oracle(torch, n):
+@pytest.mark.parametrize("variant", ["valu", "mfma"])
+@pytest.mark.parametrize("n", [1, 63, 1000, 1001, 4096])
+def test_gemv_dense_matches_oracle(torch, n, variant):
+    """Both dense kernels (one wave per row; the matrix cores) against the
+    oracle's product: one row, a partial 16-row tile and 32-column step,
+    several tiles with a ragged tail, and the dense workload's size."""
     from paper_2205_07805_amd import igs
     a = W.random_wellcond(n, 3) if n > 1 else np.array([[3.0]])
-    print(f"gemv dense n={n}", flush=True)
+    print(f"gemv dense n={n} variant={variant}", flush=True)
     ctx = igs.igs_create_dense(n, a, n, 0, None)
     try:
+        igs.igs_dense_variant(ctx, igs.IGS_DENSE_MFMA if variant == "mfma" else igs.IGS_DENSE_VALU)
         u = W.rhs_normal(n, 8)
         ud = torch.tensor(u, device="cuda")
         zd = torch.empty_like(ud)
         igs.igs_kernel_spmv(ctx, ud, zd)
         ref = O.as_operator(a).matvec(u)
         np.testing.assert_allclose(zd.cpu().numpy(), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+    finally:
+        igs.igs_destroy(ctx)
+
+
+def test_dense_variant_rejects_csr_and_unknown(torch):
+    from paper_2205_07805_amd import igs
+    ctx = _ctx_csr(W.convdiff2d(8, 1.0))
+    try:
+        with pytest.raises(igs.IgsError):
+            igs.igs_dense_variant(ctx, igs.IGS_DENSE_MFMA)
+    finally:
+        igs.igs_destroy(ctx)
+    ctx = igs.igs_create_dense(4, np.eye(4), 4, 0, None)
+    try:
+        with pytest.raises(igs.IgsError):
+            igs.igs_dense_variant(ctx, 7)
     finally:
         igs.igs_destroy(ctx)
 
