@@ -368,11 +368,13 @@ int igs_anorm_estimate(igs_ctx *ctx, double *anorm_out);
 /* Kernel of the dense operator apply z = A u (Section 1's real n x n A):
  *   IGS_DENSE_VALU: one wavefront per row, 16-byte loads, a wave sum;
  *   IGS_DENSE_MFMA: the matrix cores (v_mfma_f64_16x16x4f64), a block per 16
- *                   rows, the vector as the A operand of each product.
- * Both are bound by the matrix's bytes; the default is the faster one on
- * MI355X (IGS_DENSE_DEFAULT).  Errors: IGS_EINVAL (not a dense context, or
- * an unknown variant). */
-enum { IGS_DENSE_VALU = 0, IGS_DENSE_MFMA = 1 };
+ *                   rows, the vector as the A operand of each product;
+ *   IGS_DENSE_LDS:  the vector staged in shared memory once per block of 16
+ *                   rows (n <= 8192).
+ * All are bound by the matrix's bytes; a context starts with the fastest on
+ * MI355X.  Errors: IGS_EINVAL (not a dense context, an unknown variant, or
+ * IGS_DENSE_LDS with n > 8192). */
+enum { IGS_DENSE_VALU = 0, IGS_DENSE_MFMA = 1, IGS_DENSE_LDS = 2 };
 int igs_dense_variant(igs_ctx *ctx, int variant);
 
 /* ---- Step kernels on caller buffers (unit tests of each hot-path step) --- */

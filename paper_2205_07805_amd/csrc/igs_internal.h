@@ -12,6 +12,7 @@ constexpr int kReduceWaves = kReduceThreads / kWave;
 constexpr int kUpdateThreads = 256;
 constexpr int kUpdateRows = 4;          // rows per thread in the update / x-update passes
 constexpr int kMaxBlocks = 2048;        // most blocks of a kernel that writes partial sums
+constexpr long long kGemvLdsMax = 8192;   // most columns (lda) of the shared-memory dense kernel
 constexpr int kMaxGroups = 64;          // rows of the group-partial buffer (8 are used; the rest
                                         // is scratch for the explicit-norm fallback)
 
@@ -74,7 +75,8 @@ struct Op {
   const double* vals;
   const double* A;     // dense (columns n..lda-1 of every row hold zeros)
   long long lda;
-  int dense_mfma;      // dense: 1 = the matrix-core kernel, 0 = one wave per row
+  int dense_mfma;      // dense: 0 = one wave per row, 1 = the matrix cores,
+                       // 2 = x staged in shared memory (lda <= kGemvLdsMax)
   int lpr;             // CSR lanes per row
   const float* vals32; // CSR values rounded to FP32 (mixed precision; may be null)
   int rpg;             // CSR rows per lane group (0: the default for lpr; set by the tuner)
@@ -116,6 +118,15 @@ struct Work {
   // doubles); pre_on = 0: every update block forms them itself.
   double* pre;
   int pre_on;
+  // 1: a small system's update may split the columns of a tile over the
+  // waves of a block (per-row sums then run over four quarters of the
+  // columns).  Off where results must match the batched kernels bit for bit,
+  // whose row sums run over the columns in order: on for dense operators
+  // only, which are never batched.
+  int col_split;
+  // The fused reduction's column split of the current launch (set by its
+  // launcher; <= 1: none).
+  int red_csplit;
 };
 
 // Groups of the first level of the deterministic grid reduction for a grid

@@ -20,6 +20,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -384,6 +385,66 @@ __global__ __launch_bounds__(256) void gemv_dense_kernel(long long n, const doub
   if (lane == 0) y[row] = (bsub != nullptr) ? bsub[row] - acc : acc;
 }
 
+// Dense row-major operator with x staged in shared memory: a block of 4 waves
+// takes 16 rows, 4 per wave, and copies x (zeros past n) into shared memory
+// once, so x crosses the caches once per block instead of once per row.
+// Each lane reads 16-byte vectors of its wave's 4 rows, two column steps per
+// round (8 loads in flight), and the wave sums each row at the end.  Needs
+// lda even with zeros in columns n .. lda - 1 and lda doubles of shared
+// memory.
+constexpr int kGemvLdsRows = 16;
+__global__ __launch_bounds__(256) void gemv_lds_kernel(long long n, const double* __restrict__ A,
+                                                       long long lda,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y,
+                                                       const double* __restrict__ bsub,
+                                                       const Ctl* __restrict__ gate, int gate_j) {
+  extern __shared__ double xs[];
+  if (gate != nullptr && !ctl_runs(gate, gate_j)) return;
+  for (long long k = threadIdx.x; k < lda; k += blockDim.x) xs[k] = (k < n) ? x[k] : 0.0;
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const long long rbase = (long long)blockIdx.x * kGemvLdsRows + 4LL * wave;
+  const double* __restrict__ rows[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) rows[r] = A + min(rbase + r, n - 1) * lda;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const long long nvec = lda / 2;
+  long long c = lane;
+  for (; c + kWave < nvec; c += 2 * kWave) {
+    dvec2 a0[4], a1[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a0[r] = ld_stream2(rows[r] + 2 * c);
+      a1[r] = ld_stream2(rows[r] + 2 * (c + kWave));
+    }
+    const dvec2 x0 = *reinterpret_cast<const dvec2*>(xs + 2 * c);
+    const dvec2 x1 = *reinterpret_cast<const dvec2*>(xs + 2 * (c + kWave));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[r] = fma(a0[r][0], x0[0], acc[r]);
+      acc[r] = fma(a0[r][1], x0[1], acc[r]);
+      acc[r] = fma(a1[r][0], x1[0], acc[r]);
+      acc[r] = fma(a1[r][1], x1[1], acc[r]);
+    }
+  }
+  for (; c < nvec; c += kWave) {
+    const dvec2 xv = *reinterpret_cast<const dvec2*>(xs + 2 * c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const dvec2 av = ld_stream2(rows[r] + 2 * c);
+      acc[r] = fma(av[0], xv[0], acc[r]);
+      acc[r] = fma(av[1], xv[1], acc[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double sr = wave_sum(acc[r]);
+    const long long row = rbase + r;
+    if (lane == 0 && row < n) y[row] = (bsub != nullptr) ? bsub[row] - sr : sr;
+  }
+}
+
 // Dense row-major operator on the matrix cores (v_mfma_f64_16x16x4f64).  A
 // block owns 16 rows; its 8 waves take interleaved steps of 32 columns.  In
 // a step, lane l (r = l % 16, q = l / 16) reads the 8 entries of row
@@ -527,7 +588,14 @@ static hipError_t op_apply(const Op& op, const TA* x, TY* y, const TA* bsub, con
                            int gate_j, hipStream_t s) {
   if (op.dense) {
     if constexpr (std::is_same<TA, double>::value && std::is_same<TY, double>::value) {
-      if (op.dense_mfma) {
+      if (op.dense_mfma == 2) {
+        if (op.lda % 2 != 0 || op.lda > kGemvLdsMax) return hipErrorInvalidValue;
+        const unsigned grid = (unsigned)((op.n + kGemvLdsRows - 1) / kGemvLdsRows);
+        hipLaunchKernelGGL(gemv_lds_kernel, dim3(grid), dim3(256), sizeof(double) * op.lda, s,
+                           op.n, op.A, op.lda, x, y, bsub, gate, gate_j);
+        return hipGetLastError();
+      }
+      if (op.dense_mfma == 1) {
         if (op.lda % 32 != 0) return hipErrorInvalidValue;
         const unsigned grid = (unsigned)((op.n + 15) / 16);
         hipLaunchKernelGGL(gemv_mfma_kernel, dim3(grid), dim3(kGemvWaves * 64), 0, s, op.n, op.A,
@@ -1552,18 +1620,24 @@ __device__ __forceinline__ void reduce_body(
   const int ncol = j + 1;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const long long r0 = (long long)gr.bid * rows_per_block;
+  // column split (small systems, w.red_csplit > 1): block bid takes row
+  // block bid / cs and the columns [cb0, cb1) of part bid % cs; its partial
+  // sums of the other columns are zero
+  const int cs = (!ZS && !raw && w.red_csplit > 1) ? w.red_csplit : 1;
+  const int cb = gr.bid % cs;
+  const int cb0 = (int)((long long)ncol * cb / cs), cb1 = (int)((long long)ncol * (cb + 1) / cs);
+  const long long r0 = (long long)(gr.bid / cs) * rows_per_block;
   const long long r1 = min(n, r0 + rows_per_block);
   const T* __restrict__ z = ZS ? zsh : (raw ? zraw : zvec<T>(w));
   const long long zoff = ZS ? r0 : 0;
   const T* __restrict__ u = V + (size_t)j * ldv;
-  const int nchunk = (ncol + cpw - 1) / cpw;
+  const int nchunk = (cb1 - cb0 + cpw - 1) / cpw;
   const int cw = wave % wc;
   const int rw = wave / wc;
   if (rw < wr) {
     for (int ch = cw; ch < nchunk; ch += wc) {
-      const int c0 = ch * cpw;
-      const int nc = min(cpw, ncol - c0);
+      const int c0 = cb0 + ch * cpw;
+      const int nc = min(cpw, cb1 - c0);
       double ap[CPW], aq[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
@@ -1587,8 +1661,10 @@ __device__ __forceinline__ void reduce_body(
   if (wave == 0) {
     double* part = w.part + (size_t)gr.bid * w.pstride;
     for (int v = lane; v < 2 * ncol; v += kWave) {
+      const int col = v < ncol ? v : v - ncol;
       double acc = 0.0;
-      for (int k = 0; k < wr; ++k) acc += lds[(size_t)k * 2 * ncol + v];
+      if (col >= cb0 && col < cb1)
+        for (int k = 0; k < wr; ++k) acc += lds[(size_t)k * 2 * ncol + v];
       put_partial(part + v, acc);
     }
   }
@@ -1695,16 +1771,39 @@ static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z
   }
   if (w.tune && (w.tune[j] & 1) && cap > 1) cap /= 2;
   reduce_rows(sh, n, cap);
+  // A small system with many columns (allowed by the solve): split the
+  // columns over several blocks per row block, at least 8 columns each, so
+  // that about half the CUs take part.
+  int csplit = 1;
+  size_t lds_launch = lds;
+  ReduceKernel<T> kl = k;
+  if (!raw_out && w.col_split) {
+    const int cus = resident_blocks(nullptr, 0, 0);
+    const int want = (cus / 2) / sh.nblocks;
+    csplit = std::min((ncol + 7) / 8, want);
+    if (csplit > 1) {
+      ReduceShape sc = reduce_columns((ncol + csplit - 1) / csplit);
+      sc.rows_per_block = sh.rows_per_block;
+      sc.nblocks = sh.nblocks * csplit;
+      sh = sc;
+      lds_launch = reduce_lds_bytes(sh, ncol);
+      kl = pick_reduce<T>(sh.tcpw, vec, with_z);
+      if (kl == nullptr) return hipErrorInvalidValue;
+    } else {
+      csplit = 1;
+    }
+  }
   if (nblocks_out) *nblocks_out = sh.nblocks;
   Work wa = w;
+  wa.red_csplit = csplit;
   long long na = n, rpb = sh.rows_per_block, ldva = ldv_raw;
   int ja = j, cpw = sh.cpw, wc = sh.wc, wr = sh.wr;
   const T* va = Vraw;
   const T* za = zraw;
   double* oa = raw_out;
   void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &va, &ldva, &za, &oa};
-  return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(sh.nblocks), dim3(kReduceThreads),
-                         args, lds, s);
+  return hipLaunchKernel(reinterpret_cast<const void*>(kl), dim3(sh.nblocks), dim3(kReduceThreads),
+                         args, lds_launch, s);
 }
 
 hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,
@@ -2085,9 +2184,98 @@ __device__ __forceinline__ void update_body(
   const double rj = need_r ? r1[j] : 0.0;
   T* __restrict__ vj = V + (size_t)j * ldv;
   T* __restrict__ un = V + (size_t)(j + 1) * ldv;
+  double s2 = 0.0;  // ||w||^2 partial (fallback only)
+  if constexpr (NV == 0) {
+    // Column split, for systems too small to give every CU a tile of the
+    // row-vector pass: a tile of 64 W rows per block, each of the 4 waves
+    // forms the partial sums of its quarter of the columns for every row of
+    // the tile (8 loads in flight per lane), and wave 0 adds the quarters in
+    // order and writes.  Four times the blocks, a quarter of the column
+    // batches on each block's latency chain.
+    static_assert(VEC, "the column split takes 16-byte row vectors");
+    constexpr int kNw = kUpdateThreads / kWave;
+    constexpr long long kTileS = (long long)kWave * W;
+    __shared__ double pa[kNw][kTileS], pb[kNw][kTileS];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int c0 = (int)((long long)j * wave / kNw), c1 = (int)((long long)j * (wave + 1) / kNw);
+    const long long ntiles = (n + kTileS - 1) / kTileS;
+    for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
+      const long long p = tile * kTileS + (long long)W * lane;
+      const bool full = p + W <= n;
+      double a[W], b[W];
+#pragma unroll
+      for (int e = 0; e < W; ++e) a[e] = b[e] = 0.0;
+      auto use = [&](const double* v, int c) {
+        const double tc = HAS_T ? t[c] : 0.0;
+        const double rc = r1[c];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          if (HAS_T) a[e] = fma(v[e], tc, a[e]);
+          b[e] = fma(v[e], rc, b[e]);
+        }
+      };
+      int c = c0;
+      if (full) {
+        for (; c + 8 <= c1; c += 8) {
+          VT v[8];
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) v[cc] = ld16_stream<T>(V + (size_t)(c + cc) * ldv + p);
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) {
+            double d[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) d[e] = (double)v[cc][e];
+            use(d, c + cc);
+          }
+        }
+        for (; c < c1; ++c) {
+          const VT v = ld16_stream<T>(V + (size_t)c * ldv + p);
+          double d[W];
+#pragma unroll
+          for (int e = 0; e < W; ++e) d[e] = (double)v[e];
+          use(d, c);
+        }
+      } else {
+        for (; c < c1; ++c) {
+          double d[W];
+#pragma unroll
+          for (int e = 0; e < W; ++e) d[e] = (p + e < n) ? (double)V[(size_t)c * ldv + p + e] : 0.0;
+          use(d, c);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < W; ++e) {
+        pa[wave][W * lane + e] = a[e];
+        pb[wave][W * lane + e] = b[e];
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          const long long r = p + e;
+          if (r >= n) continue;
+          double sa = pa[0][W * lane + e], sb = pb[0][W * lane + e];
+#pragma unroll
+          for (int q = 1; q < kNw; ++q) {
+            sa += pa[q][W * lane + e];
+            sb += pb[q][W * lane + e];
+          }
+          if (unscaled) {
+            const double wv = (double)vj[r] - sa;
+            vj[r] = (T)wv;
+            s2 = fma(wv, wv, s2);
+          } else {
+            const double v = ((double)vj[r] - sa) * ig;
+            vj[r] = (T)v;
+            if (need_r) un[r] = (T)((double)z[r] * ig - sb - v * rj);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  } else {
   constexpr long long kTile = update_tile_rows<T, NV>();
   const long long ntiles = (n + kTile - 1) / kTile;
-  double s2 = 0.0;  // ||w||^2 partial (fallback only)
   for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
     if constexpr (VEC) {
       // Full tile: the thread owns the row vectors at p_k = W t + k W
@@ -2255,6 +2443,7 @@ __device__ __forceinline__ void update_body(
       }
     }
   }
+  }
   if (!fallback) return;
   // Lagged norm cancelled: w = u - V t is stored unnormalised; its explicit
   // norm comes from a grid reduction (group totals in rows 8.. of gpart, so
@@ -2339,13 +2528,17 @@ using UpdateKernel = void (*)(Work, long long, int, int, T*, long long, const T*
                               const double*, double, int);
 
 // Row vectors per thread of the single-instance update: the largest of 4, 2
-// and 1 whose tiles still number at least one per CU.
+// and 1 whose tiles still number at least one per CU; 0 (the column split)
+// when the solve allows it and even one vector per thread gives fewer tiles
+// than half the CUs.
 template <typename T>
-static int update_nv(long long n) {
+static int update_nv(long long n, bool col_split) {
   const long long cus = resident_blocks(nullptr, 0, 0);
   if ((n + update_tile_rows<T, 4>() - 1) / update_tile_rows<T, 4>() >= cus) return 4;
   if ((n + update_tile_rows<T, 2>() - 1) / update_tile_rows<T, 2>() >= cus) return 2;
-  return 1;
+  if (!col_split || (n + update_tile_rows<T, 1>() - 1) / update_tile_rows<T, 1>() >= cus / 2)
+    return 1;
+  return 0;
 }
 
 template <typename T>
@@ -2360,7 +2553,7 @@ static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t,
   const bool vec = (ldv % Vec16<T>::W == 0) && (reinterpret_cast<uintptr_t>(Vp) % 16 == 0) &&
                    (reinterpret_cast<uintptr_t>(zp) % 16 == 0);
   // the longest runs per column that still give every CU a tile
-  const int nv = vec ? update_nv<T>(n) : 2;
+  const int nv = vec ? update_nv<T>(n, raw == 0 && w.col_split) : 2;
   UpdateKernel<T> k;
   long long tile_rows;
   if (nv == 4) {
@@ -2369,6 +2562,9 @@ static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t,
   } else if (nv == 1) {
     k = has_t ? update_kernel<true, true, T, 1> : update_kernel<false, true, T, 1>;
     tile_rows = update_tile_rows<T, 1>();
+  } else if (nv == 0) {
+    k = has_t ? update_kernel<true, true, T, 0> : update_kernel<false, true, T, 0>;
+    tile_rows = (long long)kWave * Vec16<T>::W;
   } else {
     k = has_t ? (vec ? update_kernel<true, true, T, 2> : update_kernel<true, false, T, 2>)
               : (vec ? update_kernel<false, true, T, 2> : update_kernel<false, false, T, 2>);

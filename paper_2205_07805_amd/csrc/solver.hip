@@ -734,6 +734,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   w.tune = c->tune.empty() ? nullptr : c->tune.data();
   // the small products of large iterations in a kernel of their own
   w.pre_on = o.products_in_update ? 0 : 1;
+  w.col_split = c->op.dense ? 1 : 0;
   hipStream_t s = c->stream;
   c->J_first = -1;
   c->V_first_valid = 0;
@@ -980,9 +981,12 @@ extern "C" int igs_debug_copy_H(igs_ctx* c, double* H_host, int ldh, int* ncols)
 extern "C" int igs_dense_variant(igs_ctx* c, int variant) {
   if (!c) return IGS_EINVAL;
   if (!c->op.dense) return set_err(c, IGS_EINVAL, "not a dense operator");
-  if (variant != IGS_DENSE_VALU && variant != IGS_DENSE_MFMA)
-    return set_err(c, IGS_EINVAL, "variant must be IGS_DENSE_VALU or IGS_DENSE_MFMA");
-  c->op.dense_mfma = (variant == IGS_DENSE_MFMA) ? 1 : 0;
+  if (variant != IGS_DENSE_VALU && variant != IGS_DENSE_MFMA && variant != IGS_DENSE_LDS)
+    return set_err(c, IGS_EINVAL, "variant must be IGS_DENSE_VALU, IGS_DENSE_MFMA or IGS_DENSE_LDS");
+  if (variant == IGS_DENSE_LDS && c->op.lda > igs::kGemvLdsMax)
+    return set_err(c, IGS_EINVAL, "IGS_DENSE_LDS holds at most %lld columns in shared memory",
+                   (long long)igs::kGemvLdsMax);
+  c->op.dense_mfma = variant;
   return IGS_OK;
 }
 
@@ -1551,6 +1555,7 @@ void batch_row(Batch& B, int k, const BatchParams& p) {
   I.w = M.c->w;
   I.w.fp32 = p.fp32;
   I.w.pre_on = 0;   // batched updates form the small products themselves
+  I.w.col_split = 0;
   I.op = M.c->op;
   I.n = M.c->n;
   I.b = M.b;

@@ -224,7 +224,7 @@ def igs_kernel_reduce_noalloc(V, ldv, n, j, z, PQ, hip_stream=None) -> None:
         _ptr(V), int(ldv), int(n), int(j), _ptr(z), _ptr(PQ), _ptr(hip_stream)), None)
 
 
-IGS_DENSE_VALU, IGS_DENSE_MFMA = 0, 1
+IGS_DENSE_VALU, IGS_DENSE_MFMA, IGS_DENSE_LDS = 0, 1, 2
 
 
 def igs_dense_variant(ctx, variant) -> None:

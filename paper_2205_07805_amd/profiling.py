@@ -61,11 +61,11 @@ def family(name: str) -> str | None:
     s = short_name(name)
     if not s.startswith("igs::"):
         return None
-    for key in ("spmv_csr_kernel", "spmv_ell_kernel", "gemv_dense_kernel"):
+    for key in ("spmv_csr_kernel", "spmv_ell_kernel", "gemv_dense_kernel", "gemv_mfma_kernel"):
         if key in s:
             return "spmv"
     for key, fam in (("opreduce_kernel", "opreduce"), ("reduce_kernel", "reduce"),
-                     ("update_kernel", "update"),
+                     ("update_kernel", "update"), ("coef_kernel", "coef"),
                      ("xupdate_kernel", "xupdate"), ("lsq_kernel", "lsq"),
                      ("cycle_begin_kernel", "cycle_begin"), ("bnorm_kernel", "bnorm")):
         if key in s:
@@ -115,7 +115,7 @@ def label_launches(rows):
             j += 1
             out.append((solve, fam, j, cycle))
             continue
-        out.append((solve, fam, j if fam == "update" else None, cycle))
+        out.append((solve, fam, j if fam in ("update", "coef") else None, cycle))
     return out
 
 
@@ -138,7 +138,7 @@ def trace_summary(trace_csv: str, solves=None) -> str:
         if l is None or not (lo <= l[0] < hi):
             continue
         us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-        if (l[1] in ("reduce", "opreduce", "update") and us < NOOP_US) or \
+        if (l[1] in ("reduce", "opreduce", "update", "coef") and us < NOOP_US) or \
                 (l[1] == "spmv" and (l[3], l[2]) in idle):
             noop[l[1]] += 1
             continue
@@ -153,14 +153,14 @@ def trace_summary(trace_csv: str, solves=None) -> str:
     for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"{k:12s} {len(v):8d} {sum(v) / len(v):9.2f} {sum(v) / 1e3:9.2f}"
                      f"  ({100 * sum(v) / tot:4.1f}%)")
-    lines += ["", "per iteration j (average us): opreduce  reduce  update  spmv"]
+    lines += ["", "per iteration j (average us): opreduce  reduce  update  spmv  coef"]
     js = sorted({j for (_, j) in perj})
     for j in js:
         if j % 5 and j != js[-1]:
             continue
         f = lambda k: (sum(perj[(k, j)]) / len(perj[(k, j)])) if perj.get((k, j)) else float("nan")
         lines.append(f"  j={j:3d} {f('opreduce'):8.2f} {f('reduce'):8.2f} {f('update'):8.2f} "
-                     f"{f('spmv'):8.2f}")
+                     f"{f('spmv'):8.2f} {f('coef'):8.2f}")
     return "\n".join(lines)
 
 

@@ -66,10 +66,11 @@ def test_spmv_csr_matches_oracle(torch, case):
         igs.igs_destroy(ctx)
 
 
-@pytest.mark.parametrize("variant", ["valu", "mfma"])
+@pytest.mark.parametrize("variant", ["valu", "mfma", "lds"])
 @pytest.mark.parametrize("n", [1, 63, 1000, 1001, 4096])
 def test_gemv_dense_matches_oracle(torch, n, variant):
-    """Both dense kernels (one wave per row; the matrix cores) against the
+    """The dense kernels (one wave per row; the matrix cores; the vector in
+    shared memory) against the
     oracle's product: one row, a partial 16-row tile and 32-column step,
     several tiles with a ragged tail, and the dense workload's size."""
     from paper_2205_07805_amd import igs
@@ -77,7 +78,8 @@ def test_gemv_dense_matches_oracle(torch, n, variant):
     print(f"gemv dense n={n} variant={variant}", flush=True)
     ctx = igs.igs_create_dense(n, a, n, 0, None)
     try:
-        igs.igs_dense_variant(ctx, igs.IGS_DENSE_MFMA if variant == "mfma" else igs.IGS_DENSE_VALU)
+        igs.igs_dense_variant(ctx, {"valu": igs.IGS_DENSE_VALU, "mfma": igs.IGS_DENSE_MFMA,
+                                    "lds": igs.IGS_DENSE_LDS}[variant])
         u = W.rhs_normal(n, 8)
         ud = torch.tensor(u, device="cuda")
         zd = torch.empty_like(ud)
