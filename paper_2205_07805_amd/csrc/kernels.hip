@@ -1603,6 +1603,17 @@ template <typename T> __host__ __device__ T* zvec(const Work& w);
 template <> __host__ __device__ double* zvec<double>(const Work& w) { return w.z; }
 template <> __host__ __device__ float* zvec<float>(const Work& w) { return w.z32; }
 
+// Shared memory of the reduction (doubles): the wave partials of the older
+// columns (wr rows of 2 ncol), or the totals and the grid-reduction scratch
+// (2 ncol + max(threads, 2 ncol)), whichever is larger; then the fresh
+// columns' partial sums (4 per wave).
+__host__ __device__ __forceinline__ size_t fresh_lds_offset(int wr, int ncol) {
+  const size_t nv = (size_t)2 * ncol;
+  const size_t a = (size_t)wr * nv;
+  const size_t b = nv + (nv > (size_t)kReduceThreads ? nv : (size_t)kReduceThreads);
+  return a > b ? a : b;
+}
+
 // ZS: z is the block's own rows of A u in shared memory (zsh[r - r0]), formed
 // by the fused operator apply; sm: the shared memory of the reduction (the
 // dynamic shared memory when null).
@@ -1631,13 +1642,35 @@ __device__ __forceinline__ void reduce_body(
   const T* __restrict__ z = ZS ? zsh : (raw ? zraw : zvec<T>(w));
   const long long zoff = ZS ? r0 : 0;
   const T* __restrict__ u = V + (size_t)j * ldv;
-  const int nchunk = (cb1 - cb0 + cpw - 1) / cpw;
+  // Without a column split, the columns the previous kernels have just
+  // written, v_{j-1} and u_j, are summed first in a pass of their own by all
+  // waves over the block's rows (a freshly written column read inside a
+  // stream of many others slows the whole stream), and the column groups
+  // below stream the older columns [0, f0) only.
+  const int f0 = (cs == 1) ? (j >= 1 ? j - 1 : 0) : ncol;
+  double* fr = lds + fresh_lds_offset(wr, ncol);   // [waves][4] fresh partial sums
+  if (cs == 1) {
+    double ap[2] = {0.0, 0.0}, aq[2] = {0.0, 0.0};
+    stream_group<2, VEC, Z, T>(ncol - f0, V + (size_t)f0 * ldv, ldv, u, z, zoff, r0, r1, wave,
+                               kReduceWaves, lane, ap, aq);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double sp = wave_sum(ap[c]);
+      const double sq = wave_sum(aq[c]);
+      if (lane == 0) {
+        fr[wave * 4 + c] = sp;
+        fr[wave * 4 + 2 + c] = sq;
+      }
+    }
+  }
+  const int cend = (cs == 1) ? f0 : cb1;
+  const int nchunk = (cend - cb0 + cpw - 1) / cpw;
   const int cw = wave % wc;
   const int rw = wave / wc;
   if (rw < wr) {
     for (int ch = cw; ch < nchunk; ch += wc) {
       const int c0 = cb0 + ch * cpw;
-      const int nc = min(cpw, cb1 - c0);
+      const int nc = min(cpw, cend - c0);
       double ap[CPW], aq[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
@@ -1663,8 +1696,13 @@ __device__ __forceinline__ void reduce_body(
     for (int v = lane; v < 2 * ncol; v += kWave) {
       const int col = v < ncol ? v : v - ncol;
       double acc = 0.0;
-      if (col >= cb0 && col < cb1)
+      if (col >= f0) {
+        // a fresh column: the waves' sums in order
+        const int k4 = (v < ncol ? 0 : 2) + (col - f0);
+        for (int k = 0; k < kReduceWaves; ++k) acc += fr[k * 4 + k4];
+      } else if (col >= cb0 && col < cb1) {
         for (int k = 0; k < wr; ++k) acc += lds[(size_t)k * 2 * ncol + v];
+      }
       put_partial(part + v, acc);
     }
   }
@@ -1691,11 +1729,12 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
 // Shared memory of the fused reduction: the wave partials; then the totals
 // (2 ncol) followed by the grid-reduction scratch.
 static size_t reduce_lds_bytes(const ReduceShape& s, int ncol) {
-  const size_t nv = (size_t)2 * ncol;
-  const size_t a = (size_t)s.wr * nv;
-  const size_t b = nv + (nv > (size_t)kReduceThreads ? nv : (size_t)kReduceThreads);
-  return (a > b ? a : b) * sizeof(double);
+  return (fresh_lds_offset(s.wr, ncol) + 4 * kReduceWaves) * sizeof(double);
 }
+
+// Column groups of the reduction of iteration j: the older columns [0, j-1)
+// (the fresh ones, v_{j-1} and u_j, have a pass of their own).
+static ReduceShape reduce_shape(int j) { return reduce_columns(j >= 2 ? j - 1 : 1); }
 
 // Blocks of `kernel` that are resident at once on the current device with
 // `threads` threads and `lds` bytes of dynamic shared memory (cached); with
@@ -1746,7 +1785,7 @@ static hipError_t reduce_dispatch(const Work& w, long long n, int j, bool with_z
                                   long long ldv_raw, const T* zraw, double* raw_out,
                                   hipStream_t s, int* nblocks_out) {
   const int ncol = j + 1;
-  ReduceShape sh = reduce_columns(ncol);
+  ReduceShape sh = reduce_shape(j);
   const size_t lds = reduce_lds_bytes(sh, ncol);
   // 16-byte row vectors need a leading dimension of whole vectors and
   // 16-byte aligned columns
@@ -1950,7 +1989,7 @@ static FusedLaunch opreduce_plan(const Op& op, const Work& w, long long n, int j
       reinterpret_cast<uintptr_t>(V) % 16 != 0 || w.ldv % Vec16<T>::W != 0)
     return f;
   const int ncol = j + 1;
-  ReduceShape sh = reduce_columns(ncol);
+  ReduceShape sh = reduce_shape(j);
   const size_t red_lds = reduce_lds_bytes(sh, ncol);
   // the separate reduction's grid (reduce_dispatch)
   int cap = resident_blocks(reinterpret_cast<const void*>(pick_reduce<T>(sh.tcpw, true, true)),
@@ -2052,7 +2091,7 @@ hipError_t launch_reduce_noalloc(const double* V, long long ldv, long long n, in
     if (d.err != hipSuccess) return;
     d.ptr = static_cast<double*>(p);
     for (int ncol = 1; ncol <= kNoAllocMaxCols; ++ncol) {
-      const ReduceShape sh = reduce_columns(ncol);
+      const ReduceShape sh = reduce_shape(ncol - 1);
       const size_t lds = reduce_lds_bytes(sh, ncol);
       for (int vec = 0; vec < 2; ++vec)
         (void)resident_blocks(reinterpret_cast<const void*>(pick_reduce<double>(sh.tcpw, vec, true)),
@@ -3154,7 +3193,7 @@ static const void* pick_reduce_batch(int tcpw, bool z) {
 template <typename T>
 static hipError_t batch_reduce_t(const BatchRun& r, int j, bool with_z, int* ngroups) {
   const int ncol = j + 1;
-  const ReduceShape sh0 = reduce_columns(ncol);
+  const ReduceShape sh0 = reduce_shape(j);
   const size_t lds = reduce_lds_bytes(sh0, ncol);
   if (!batch_vec<T>(r)) return hipErrorInvalidValue;
   const void* kern = pick_reduce_batch<T>(sh0.tcpw, with_z);
