@@ -322,13 +322,16 @@ def main():
     workload = f"convdiff3d_N{args.grid}_Pe50_gmres{args.restart}_tol{args.tol:g}"
 
     if args.copy_calibration:
-        src = torch.ones(32 * 2**20, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {src.numel() * 8} bytes read and written per launch")
-        del src, dst
+        # plain device copies of known size (256 MiB, then 64 MiB as a
+        # cross-check of the scale) before any solver kernel
+        for mib in (256, 64):
+            src = torch.ones(mib * 2**20 // 8, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"[bench] calibration copy: {src.numel() * 8} bytes read and written per launch")
+            del src, dst
 
     s = Solver(a)
     b_d = torch.as_tensor(b, device=dev)

@@ -147,6 +147,10 @@ hipError_t launch_residual(const Op& op, const double* b, const double* x, const
 hipError_t launch_spmv32(const Op& op, const float* u, float* z, const Ctl* gate, int j,
                          hipStream_t s);
 hipError_t launch_round_to_float(const double* src, float* dst, long long count, hipStream_t s);
+// The column-major ELL form of a CSR operator with rows of at most K <= 8
+// entries (device arrays; ec, ev hold K n entries).
+hipError_t launch_csr_to_ell(long long n, int K, const int* rp, const int* ci, const double* va,
+                             int* ec, double* ev, hipStream_t s);
 hipError_t launch_bnorm(const double* b, const double* x, long long n, const Work& w,
                         hipStream_t s);
 hipError_t launch_reduce(const Work& w, long long n, int j, bool with_z, hipStream_t s,

@@ -567,9 +567,9 @@ __global__ __launch_bounds__(256) void spmv_ell_kernel(long long n, const int* _
 template <typename TA> __host__ __device__ const TA* op_vals(const Op& op);
 template <> __host__ __device__ const double* op_vals<double>(const Op& op) { return op.vals; }
 template <> __host__ __device__ const float* op_vals<float>(const Op& op) { return op.vals32; }
-template <typename TA> const TA* ell_vals(const Op& op);
-template <> const double* ell_vals<double>(const Op& op) { return op.ell_val; }
-template <> const float* ell_vals<float>(const Op& op) { return op.ell_val32; }
+template <typename TA> __host__ __device__ const TA* ell_vals(const Op& op);
+template <> __host__ __device__ const double* ell_vals<double>(const Op& op) { return op.ell_val; }
+template <> __host__ __device__ const float* ell_vals<float>(const Op& op) { return op.ell_val32; }
 
 // Lanes per row LPR (a power of two near the mean row length) and rows per
 // lane group RPG: up to 4 rows while a group is at most 8 lanes wide.
@@ -688,6 +688,32 @@ hipError_t launch_round_to_float(const double* src, float* dst, long long count,
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(round_to_float_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst,
                      count);
+  return hipGetLastError();
+}
+
+// The column-major ELL form of a CSR operator whose rows hold at most K
+// entries: entry k of row i at k n + i, the slots past a row's end column 0
+// and value 0 (the layout igs_create builds on the host).  One thread per
+// row; the stores of each slot are consecutive over the rows.
+__global__ void csr_to_ell_kernel(long long n, int K, const int* __restrict__ rp,
+                                  const int* __restrict__ ci, const double* __restrict__ va,
+                                  int* __restrict__ ec, double* __restrict__ ev) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = rp[i], e = rp[i + 1];
+  for (int k = 0; k < K; ++k) {
+    const int idx = b + k;
+    const bool ok = idx < e;
+    ec[(long long)k * n + i] = ok ? ci[idx] : 0;
+    ev[(long long)k * n + i] = ok ? va[idx] : 0.0;
+  }
+}
+
+hipError_t launch_csr_to_ell(long long n, int K, const int* rp, const int* ci, const double* va,
+                             int* ec, double* ev, hipStream_t s) {
+  if (n <= 0 || K < 1 || K > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(csr_to_ell_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, K,
+                     rp, ci, va, ec, ev);
   return hipGetLastError();
 }
 
@@ -3117,6 +3143,89 @@ hipError_t batch_bnorm(const BatchRun& r) {
   return launch_map(reinterpret_cast<const void*>(bnorm_batch_kernel), m, 256, 0, args, r.stream);
 }
 
+// The operator apply of the instances that hold an ELL form, RPT rows per
+// thread: the products and additions of spmv_ell_kernel (and so of the
+// CSR kernel with 8 lanes per row), with the slot count K read from the
+// instance; so z is bit-identical to a lone solve's.
+template <int RPT, typename T>
+__global__ __launch_bounds__(256) void spmv_ell_batch_kernel(const Inst* __restrict__ tab,
+                                                             BatchMap map, int j) {
+#pragma clang fp contract(off)
+  typedef int IV __attribute__((ext_vector_type(RPT)));
+  typedef T AV __attribute__((ext_vector_type(RPT)));
+  const MapEntry e = map_find(map);
+  const int bid = (int)blockIdx.x - e.start;
+  if (bid >= e.nblk) return;
+  const Inst* I = tab + e.inst;
+  const Work w = I->w;
+  if (!ctl_runs(w.ctl, j)) return;
+  const long long n = I->n;
+  const long long row0 = ((long long)bid * blockDim.x + threadIdx.x) * RPT;
+  if (row0 >= n) return;
+  const int K = I->op.ell_k;
+  const int* __restrict__ col = I->op.ell_col;
+  const T* __restrict__ val = ell_vals<T>(I->op);
+  const T* __restrict__ x = basis<T>(w) + (size_t)j * w.ldv;
+  T* __restrict__ y = zvec<T>(w);
+  IV c[8];
+  AV v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < K) {
+      c[k] = *reinterpret_cast<const IV*>(col + (long long)k * n + row0);
+      v[k] = *reinterpret_cast<const AV*>(val + (long long)k * n + row0);
+    } else {
+      c[k] = IV(0);
+      v[k] = AV(0);
+    }
+  }
+  AV out;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    T p[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = v[k][i] * x[c[k][i]];
+    const T q0 = (p[0] + p[1]) + (p[2] + p[3]);
+    const T q1 = (p[4] + p[5]) + (p[6] + p[7]);
+    out[i] = q0 + q1;
+  }
+  __builtin_nontemporal_store(out, reinterpret_cast<AV*>(y + row0));   // see st16
+}
+
+// The instances of r with an ELL form (and no tuned CSR shape): one launch
+// for those with even n (two rows per thread), one for the others.
+template <typename T>
+static hipError_t batch_spmv_ell(const BatchRun& r, int j) {
+  for (int rpt = 2; rpt >= 1; --rpt) {
+    BatchRun sub = r;
+    sub.count = 0;
+    int nb[kMaxBatch];
+    for (int q = 0; q < r.count; ++q) {
+      const Inst& I = r.h_tab[r.act[q]];
+      const int want = (I.n % 2 == 0) ? 2 : 1;
+      if (want != rpt) continue;
+      nb[sub.count] = (int)((I.n / rpt + 255) / 256);
+      sub.act[sub.count++] = r.act[q];
+    }
+    if (sub.count == 0) continue;
+    BatchMap m;
+    build_map(m, sub, nb, nullptr);
+    const Inst* t = r.d_tab;
+    int ja = j;
+    void* args[] = {&t, &m, &ja};
+    const void* kern = (rpt == 2) ? reinterpret_cast<const void*>(spmv_ell_batch_kernel<2, T>)
+                                  : reinterpret_cast<const void*>(spmv_ell_batch_kernel<1, T>);
+    const hipError_t err = launch_map(kern, m, 256, 0, args, r.stream);
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+static bool inst_has_ell(const Inst& I) {
+  return I.op.ell_k > 0 && I.op.rpg == 0 && I.op.ell_col != nullptr &&
+         (I.w.fp32 ? I.op.ell_val32 != nullptr : I.op.ell_val != nullptr);
+}
+
 // The operator apply for the instances with lanes-per-row `lpr` (one launch
 // per distinct value; RESID: the residual r = b - A x of the cycle start).
 template <typename T, bool RESID>
@@ -3175,7 +3284,20 @@ hipError_t batch_residual(const BatchRun& r) {
 
 hipError_t batch_spmv(const BatchRun& r, int j) {
   if (r.count <= 0) return hipSuccess;
-  return batch_fp32(r) ? batch_spmv_lpr<float, false>(r, j) : batch_spmv_lpr<double, false>(r, j);
+  // members with an ELL form take the ELL kernel, the others the CSR one
+  BatchRun ell = r, csr = r;
+  ell.count = csr.count = 0;
+  for (int q = 0; q < r.count; ++q) {
+    if (inst_has_ell(r.h_tab[r.act[q]])) ell.act[ell.count++] = r.act[q];
+    else csr.act[csr.count++] = r.act[q];
+  }
+  const bool f32 = batch_fp32(r);
+  if (ell.count > 0) {
+    const hipError_t e = f32 ? batch_spmv_ell<float>(ell, j) : batch_spmv_ell<double>(ell, j);
+    if (e != hipSuccess) return e;
+  }
+  if (csr.count == 0) return hipSuccess;
+  return f32 ? batch_spmv_lpr<float, false>(csr, j) : batch_spmv_lpr<double, false>(csr, j);
 }
 
 template <typename T>

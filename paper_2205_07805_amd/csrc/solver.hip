@@ -1235,7 +1235,8 @@ namespace {
 long long request_bytes(long long n, long long nnz, int m, bool fp32) {
   const long long mm = std::min<long long>(m, n);
   return 12 * nnz + 4 * (n + 1) + 8 * n * (mm + 5) + 32 * (mm + 2) * (mm + 2) +
-         (fp32 ? 4 * nnz + 4 * n * (mm + 2) : 0);
+         96 * n +   // the ELL form (at most 8 slots)
+         (fp32 ? 4 * nnz + 4 * n * (mm + 2) + 32 * n : 0);
 }
 
 // A serving slot: a context with device capacity for CSR operators of up to
@@ -1272,7 +1273,12 @@ int slot_create(Slot& sl, long long n_cap, long long nnz_cap, int m, hipStream_t
   if (dalloc(&c->d_row_ptr, n_cap + 1) != hipSuccess ||
       dalloc(&c->d_col, std::max<long long>(nnz_cap, 1)) != hipSuccess ||
       dalloc(&c->d_vals, std::max<long long>(nnz_cap, 1)) != hipSuccess ||
-      dalloc(&sl.b, n_cap) != hipSuccess || dalloc(&sl.x, n_cap) != hipSuccess)
+      dalloc(&sl.b, n_cap) != hipSuccess || dalloc(&sl.x, n_cap) != hipSuccess ||
+      // the ELL form of operators with rows of at most 8 entries, built on
+      // the device at each binding
+      dalloc(&c->d_ell_col, 8 * n_cap) != hipSuccess ||
+      dalloc(&c->d_ell_val, 8 * n_cap) != hipSuccess ||
+      (fp32 && dalloc(&c->d_ell_val32, 8 * n_cap) != hipSuccess))
     return set_err(nullptr, IGS_ENOMEM, "device allocation of a serving slot failed");
   c->op.dense = 0;
   c->op.row_ptr = c->d_row_ptr;
@@ -1324,6 +1330,26 @@ int slot_bind(igs_ctx* c, long long n, long long nnz, const int32_t* rp, const i
   c->op.lpr = lpr;
   if (c->d_vals32) {   // FP32 values of the previous operator: round the new ones
     HIP_OR_FAIL(c, igs::launch_round_to_float(c->d_vals, c->d_vals32, nnz, c->stream));
+  }
+  // the ELL form, as igs_create keeps it (rows of at most 8 entries with 8
+  // lanes per row), converted on the device from the copied CSR arrays
+  long long kmax = 0;
+  for (long long i = 0; i < n; ++i) kmax = std::max<long long>(kmax, rp[i + 1] - rp[i]);
+  c->op.ell_k = 0;
+  c->op.ell_col = nullptr;
+  c->op.ell_val = nullptr;
+  c->op.ell_val32 = nullptr;
+  if (lpr == 8 && kmax >= 1 && kmax <= 8 && c->d_ell_col && c->d_ell_val) {
+    HIP_OR_FAIL(c, igs::launch_csr_to_ell(n, (int)kmax, c->d_row_ptr, c->d_col, c->d_vals,
+                                          c->d_ell_col, c->d_ell_val, c->stream));
+    c->op.ell_k = (int)kmax;
+    c->op.ell_col = c->d_ell_col;
+    c->op.ell_val = c->d_ell_val;
+    if (c->d_ell_val32) {
+      HIP_OR_FAIL(c, igs::launch_round_to_float(c->d_ell_val, c->d_ell_val32, kmax * n,
+                                                c->stream));
+      c->op.ell_val32 = c->d_ell_val32;
+    }
   }
   return IGS_OK;
 }

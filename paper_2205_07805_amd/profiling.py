@@ -165,19 +165,23 @@ def trace_summary(trace_csv: str, solves=None) -> str:
 
 
 def _calibration(rows):
-    """KiB the counter reads for the plain 256 MiB device copy that
-    bench.py --copy-calibration runs before any solver kernel."""
-    best = None
+    """KiB the counter reads for the plain device copies that bench.py
+    --copy-calibration runs before any solver kernel: the 256 MiB copy (the
+    largest reading) and the 64 MiB one (the smallest of the large ones, a
+    cross-check of the scale), or None for the second when absent."""
+    vals = []
     for r in rows:
         if short_name(r["Kernel_Name"]).startswith("igs::"):
             break
         if "copyBuffer" in r["Kernel_Name"]:
-            v = float(r["Counter_Value"])
-            best = v if best is None else max(best, v)
-    if best is None:
+            vals.append(float(r["Counter_Value"]))
+    if not vals:
         raise SystemExit("no calibration copy before the first solver kernel "
                          "(run bench.py with --copy-calibration)")
-    return best
+    big = max(vals)
+    # the 64 MiB copy reads about a quarter of the 256 MiB one
+    small = [v for v in vals if 0.15 * big < v < 0.4 * big]
+    return big, (max(small) if small else None)
 
 
 def algorithmic_bytes(fam, j, n, nnz, m):
@@ -195,7 +199,7 @@ def algorithmic_bytes(fam, j, n, nnz, m):
 
 def traffic(fetch_csv, write_csv, n, nnz, m, workload, solve=0, copy_bytes=256 * 2**20):
     f_rows, w_rows = _rows(fetch_csv), _rows(write_csv)
-    cf, cw = _calibration(f_rows), _calibration(w_rows)
+    (cf, cf64), (cw, cw64) = _calibration(f_rows), _calibration(w_rows)
     sf, sw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
     # pair fetch and write launches by order within (family, j)
     fam_launch = collections.defaultdict(list)
@@ -209,7 +213,10 @@ def traffic(fetch_csv, write_csv, n, nnz, m, workload, solve=0, copy_bytes=256 *
     out = {"kernel_source_sha": kernel_source_sha(), "workload": workload,
            "calibration": {"copy_bytes_read_and_written": copy_bytes,
                            "FETCH_SIZE_KiB": cf, "WRITE_SIZE_KiB": cw,
-                           "fetch_scale": sf, "write_scale": sw},
+                           "fetch_scale": sf, "write_scale": sw,
+                           # the same scale from the 64 MiB copy
+                           "fetch_scale_64MiB": (copy_bytes / 4) / (cf64 * 1024.0) if cf64 else None,
+                           "write_scale_64MiB": (copy_bytes / 4) / (cw64 * 1024.0) if cw64 else None},
            "kernels": {}}
     for fam in ("spmv", "opreduce", "reduce", "update"):
         fetch = write = alg = 0.0
