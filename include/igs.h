@@ -114,13 +114,14 @@ typedef struct igs_opts {
                              bit-identical to igs_solve_opts, except the
                              explicit norm of a lagged-norm fallback, whose
                              per-thread partial sums follow the update's
-                             tiles); <= 0: 4096                              */
+                             tiles); <= 0: 2048                              */
   int batch_update_tiles; /* batches: at least this many tiles (2,048 rows of
                              FP64, 4,096 of FP32) per block of the update.
-                             1: one tile per block; <= 0: 2                  */
+                             1 (the default; <= 0 means 1): one tile per
+                             block                                           */
   int cycle_graph;      /* 1: record the launches of a restart cycle in a HIP
                            graph once and replay it for every cycle (one
-                           launch instead of 3(m+1)+4); the graph is kept in
+                           launch instead of about 2(m+1)+4); the graph is kept in
                            the context and reused while b, x and the settings
                            stay the same.  Not with profile or two_reduce
                            (ignored there).  Results are bit-identical.      */
