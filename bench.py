@@ -209,9 +209,11 @@ def other_configs(torch, W, Solver, igs, steps=5, oracle_small=True):
                          "ms_per_solve": 1e3 * dt, "iters_per_s": info["iters"] / dt,
                          "us_per_iter": 1e6 * dt / max(info["iters"], 1),
                          "relres_true": info["relres_true"]}
-            if oracle_small and name == cases[0][0]:
-                # the oracle's whole solve of the same system on the host
-                rate, used, its, odt = oracle_rate(a, b, restart, tol, 20 * len(b))
+            if oracle_small and name in (cases[0][0], cases[2][0]):
+                # the oracle's solve of the same system on the host (the dense
+                # one: its single cycle)
+                maxit = restart if opts.get("max_cycles") == 1 else 20 * len(b)
+                rate, used, its, odt = oracle_rate(a, b, restart, tol, maxit)
                 out[name]["oracle_cpu"] = {"iters": its, "ms_per_solve": 1e3 * odt,
                                            "iters_per_s": rate, "cores": used, "kind": "oracle"}
         finally:

@@ -174,7 +174,8 @@ int igs_create(igs_ctx **out, int64_t n, int64_t nnz, const int32_t *row_ptr,
                void *hip_stream);
 
 /*
- * Create a solver context for a dense operator.
+ * Create a solver context for a dense operator (Section 1: a real n x n A;
+ * the dense non-normal test matrices of Section 5 are of this kind).
  *   A: float64, row-major, n rows of leading dimension lda >= n, finite.
  *   ptr_on_device: 0 = host memory, 1 = device memory.
  * The matrix is copied into device memory the context owns.
@@ -347,13 +348,17 @@ int igs_tune_reset(igs_ctx *ctx);
 
 /* Copy the Hessenberg matrix H (before Givens rotation) of the first cycle to
  * host memory, column-major with leading dimension ldh >= J+1; *ncols = J.
- * H_host must hold ldh * J doubles. */
+ * H_host must hold ldh * J doubles.  H is the (J+1) x J matrix of the Arnoldi
+ * relation A V_J = V_{J+1} H (Section 1; with two sweeps each column is
+ * finished from eq:Aw, Section 4). */
 int igs_debug_copy_H(igs_ctx *ctx, double *H_host, int ldh, int *ncols);
 
 /* Copy the basis V of the first cycle (J+1 columns, of which column J is
  * valid only with final_basis_vector) to a device buffer, column-major with
  * leading dimension ldv >= n; *ncols = J + 1.  V_dev must hold ldv*(J+1).
- * Needs opts.keep_first_basis = 1 in the last solve, else IGS_EINVAL. */
+ * Needs opts.keep_first_basis = 1 in the last solve, else IGS_EINVAL.  V is
+ * the orthonormal Krylov basis of the Arnoldi relation (Section 1), whose
+ * loss of orthogonality ||I - V^T V|| Section 4 bounds. */
 int igs_debug_copy_V(igs_ctx *ctx, double *V_dev, int64_t ldv, int *ncols);
 
 /* Estimate of ||A||_2 from the last solve (the backward error's
