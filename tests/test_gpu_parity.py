@@ -377,3 +377,30 @@ def test_anorm_estimate(torch):
         assert abs(est - sig) <= 1e-10 * sig, (restart, est, sig)
         assert est <= exact * (1 + 1e-12)
         assert est >= 0.99 * exact, (est, exact)
+
+
+def test_longest_restart_dense_1000(torch):
+    """The longest restart the library takes (IGS_MAX_RESTART = 512 columns):
+    one full cycle on a dense non-normal n = 1000 matrix, so the small
+    products, the packed T and H, the Givens rotations and the least squares
+    run at their largest sizes; against the oracle's cycle."""
+    from paper_2205_07805_amd import igs
+    m = igs.IGS_MAX_RESTART
+    a = W.dense_nonnormal(1000, seed_u=1, seed_w=2)
+    b = W.rhs_normal(1000, 5)
+    print(f"longest restart m={m} dense n=1000", flush=True)
+    x, rc, info, H, V = gpu(a, b, m, 0.0, 2, max_cycles=1, keep_first_basis=1,
+                            final_basis_vector=1)
+    ref = O.gmres(a, b, restart=m, tol=0.0, variant="igs1r", max_cycles=1)
+    J = info["first_cycle_J"]
+    assert J == ref.first_cycle.J == m
+    assert info["lagnorm_fallbacks"] == ref.lagnorm_fallbacks == 0
+    op = O.as_operator(a)
+    anorm = np.linalg.norm(a, 2)
+    assert D.orthogonality_loss(V[:, : J + 1]) < 1e-13
+    assert D.arnoldi_relation_residual(op, V[:, : J + 1], H, anorm) < 1e-13
+    assert_H_close(H, ref.first_cycle.H, ncols=10, tol=1e-11)
+    # the cycle's solution: both minimise the residual over the same space
+    r_gpu = np.linalg.norm(b - op.matvec(x))
+    r_ref = np.linalg.norm(b - op.matvec(ref.x))
+    assert abs(r_gpu - r_ref) <= 1e-10 * np.linalg.norm(b)
