@@ -1490,14 +1490,15 @@ static void reduce_rows(ReduceShape& s, long long n, int max_blocks) {
 
 // One wave's share of the fused reduction for NC consecutive columns of V
 // (starting at vb): over the rows of its slice of [r0, r1),
-// ap[c] += V[r, c] u[r] and (Z) aq[c] += V[r, c] z[r], products and sums in
-// FP64 whatever the element type T of V, u and z.  NC and Z are
+// ap[c] += V[r, c] u[r - uoff] and (Z) aq[c] += V[r, c] z[r - zoff], products
+// and sums in FP64 whatever the element type T of V, u and z (an offset is r0
+// when that vector is the block's own rows in shared memory, else 0).  NC and Z are
 // compile-time, so every load of a row step is unconditional and the whole
 // step is in flight before the first FMA.
 template <int NC, bool VEC, bool Z, typename T>
 __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long ldv,
-                                            const T* __restrict__ u, const T* __restrict__ z,
-                                            long long zoff, long long r0, long long r1, int rw,
+                                            const T* __restrict__ u, long long uoff,
+                                            const T* __restrict__ z, long long zoff, long long r0, long long r1, int rw,
                                             int wr, int lane, double* ap, double* aq) {
   if constexpr (VEC) {
     // Lane owns W consecutive rows (one 16-byte load per column; V
@@ -1518,7 +1519,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
 #pragma unroll
     for (int c = 0; c < NC; ++c) va[c] = vn[c] = ua;
     auto load = [&](VT& uu, VT& zz, VT* vv, long long rr) {
-      uu = ld16<T>(u + rr);
+      uu = ld16<T>(u + (rr - uoff));
       if constexpr (Z) zz = ld16<T>(z + (rr - zoff));
 #pragma unroll
       for (int c = 0; c < NC; ++c) vv[c] = ld16_stream<T>(vb + (size_t)c * ldv + rr);
@@ -1547,7 +1548,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
     }
     // the last rows of the block's range that do not fill a vector
     for (long long rr = r; rr < r1 && rr < r + W; ++rr) {
-      const double uv = (double)u[rr];
+      const double uv = (double)u[rr - uoff];
       const double zv = Z ? (double)z[rr - zoff] : 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -1565,7 +1566,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
       double uu[U], zz[U], vv[U][NC];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        uu[q] = (double)u[r + q * step];
+        uu[q] = (double)u[r + q * step - uoff];
         if constexpr (Z) zz[q] = (double)z[r + q * step - zoff];
       }
 #pragma unroll
@@ -1583,7 +1584,7 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
       }
     }
     for (; r < r1; r += step) {
-      const double uv = (double)u[r];
+      const double uv = (double)u[r - uoff];
       const double zv = Z ? (double)z[r - zoff] : 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -1599,23 +1600,23 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ vb, long long 
 // instantiation for its exact width.
 template <int CPW, bool VEC, bool Z, typename T>
 __device__ __forceinline__ void stream_group(int nc, const T* __restrict__ vb, long long ldv,
-                                             const T* __restrict__ u,
+                                             const T* __restrict__ u, long long uoff,
                                              const T* __restrict__ z, long long zoff,
                                              long long r0, long long r1, int rw, int wr,
                                              int lane, double* ap, double* aq) {
   if (nc == CPW) {
-    stream_cols<CPW, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq);
+    stream_cols<CPW, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq);
     return;
   }
   if constexpr (CPW > 1) {
     switch (nc) {
-      case 1: stream_cols<1, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
-      case 2: if constexpr (CPW > 2) stream_cols<2, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
-      case 3: if constexpr (CPW > 3) stream_cols<3, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
-      case 4: if constexpr (CPW > 4) stream_cols<4, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
-      case 5: if constexpr (CPW > 5) stream_cols<5, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
-      case 6: if constexpr (CPW > 6) stream_cols<6, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
-      case 7: if constexpr (CPW > 7) stream_cols<7, VEC, Z, T>(vb, ldv, u, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 1: stream_cols<1, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 2: if constexpr (CPW > 2) stream_cols<2, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 3: if constexpr (CPW > 3) stream_cols<3, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 4: if constexpr (CPW > 4) stream_cols<4, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 5: if constexpr (CPW > 5) stream_cols<5, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 6: if constexpr (CPW > 6) stream_cols<6, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
+      case 7: if constexpr (CPW > 7) stream_cols<7, VEC, Z, T>(vb, ldv, u, uoff, z, zoff, r0, r1, rw, wr, lane, ap, aq); break;
       default: break;
     }
   }
@@ -1641,13 +1642,15 @@ __host__ __device__ __forceinline__ size_t fresh_lds_offset(int wr, int ncol) {
 }
 
 // ZS: z is the block's own rows of A u in shared memory (zsh[r - r0]), formed
-// by the fused operator apply; sm: the shared memory of the reduction (the
-// dynamic shared memory when null).
+// by the fused operator apply, and so is u (ush[r - r0]) unless ush is null;
+// sm: the shared memory of the reduction (the dynamic shared memory when
+// null).
 template <int CPW, bool VEC, bool Z, typename T, bool ZS = false>
 __device__ __forceinline__ void reduce_body(
     Grid gr, const Work& w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr,
     const T* __restrict__ Vraw, long long ldv_raw, const T* __restrict__ zraw,
-    double* __restrict__ raw_out, double* sm = nullptr, const T* zsh = nullptr) {
+    double* __restrict__ raw_out, double* sm = nullptr, const T* zsh = nullptr,
+    const T* ush = nullptr) {
   extern __shared__ double dyn_lds[];
   double* lds = ZS ? sm : dyn_lds;
   const bool raw = (raw_out != nullptr);
@@ -1667,7 +1670,8 @@ __device__ __forceinline__ void reduce_body(
   const long long r1 = min(n, r0 + rows_per_block);
   const T* __restrict__ z = ZS ? zsh : (raw ? zraw : zvec<T>(w));
   const long long zoff = ZS ? r0 : 0;
-  const T* __restrict__ u = V + (size_t)j * ldv;
+  const T* __restrict__ u = (ZS && ush) ? ush : V + (size_t)j * ldv;
+  const long long uoff = (ZS && ush) ? r0 : 0;
   // Without a column split, the columns the previous kernels have just
   // written, v_{j-1} and u_j, are summed first in a pass of their own by all
   // waves over the block's rows (a freshly written column read inside a
@@ -1677,7 +1681,7 @@ __device__ __forceinline__ void reduce_body(
   double* fr = lds + fresh_lds_offset(wr, ncol);   // [waves][4] fresh partial sums
   if (cs == 1) {
     double ap[2] = {0.0, 0.0}, aq[2] = {0.0, 0.0};
-    stream_group<2, VEC, Z, T>(ncol - f0, V + (size_t)f0 * ldv, ldv, u, z, zoff, r0, r1, wave,
+    stream_group<2, VEC, Z, T>(ncol - f0, V + (size_t)f0 * ldv, ldv, u, uoff, z, zoff, r0, r1, wave,
                                kReduceWaves, lane, ap, aq);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -1700,7 +1704,7 @@ __device__ __forceinline__ void reduce_body(
       double ap[CPW], aq[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) ap[c] = aq[c] = 0.0;
-      stream_group<CPW, VEC, Z, T>(nc, V + (size_t)c0 * ldv, ldv, u, z, zoff, r0, r1, rw, wr,
+      stream_group<CPW, VEC, Z, T>(nc, V + (size_t)c0 * ldv, ldv, u, uoff, z, zoff, r0, r1, rw, wr,
                                    lane, ap, aq);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
@@ -1945,23 +1949,34 @@ __device__ __forceinline__ void ell_rows4(const int* __restrict__ col, const T* 
 template <int CPW, typename T>
 __global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
     Work w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr, int ell_k,
-    const int* __restrict__ ell_col, const T* __restrict__ ell_val) {
+    const int* __restrict__ ell_col, const T* __restrict__ ell_val, int u_lds) {
   extern __shared__ double lds[];
   if (!ctl_runs(w.ctl, j)) return;
   typedef T A4 __attribute__((ext_vector_type(4)));
   const Grid gr = hw_grid();
   const long long r0 = (long long)gr.bid * rows_per_block;
   const long long r1 = min(n, r0 + rows_per_block);
-  // shared memory: the block's rows of z (rows_per_block values, a multiple
-  // of 256), then the reduction's own
+  // shared memory: the block's rows of z and (u_lds) of u, rows_per_block
+  // values each (a multiple of 256), then the reduction's own
   T* zs = reinterpret_cast<T*>(lds);
-  double* sm = lds + (size_t)rows_per_block * sizeof(T) / sizeof(double);
+  T* us = u_lds ? zs + rows_per_block : nullptr;
+  double* sm = lds + (size_t)rows_per_block * (u_lds ? 2 : 1) * sizeof(T) / sizeof(double);
   const T* __restrict__ u = basis<T>(w) + (size_t)j * w.ldv;
   T* __restrict__ zg = zvec<T>(w);
+  typedef typename Vec16<T>::type VT;
+  constexpr int W = Vec16<T>::W;
   for (long long r = r0 + 4 * (long long)threadIdx.x; r < r1; r += 4LL * kReduceThreads) {
     A4 o;
     T out[4];
     ell_rows4<T>(ell_col, ell_val, n, ell_k, u, r, out);
+    // the block's own rows of u (also among the gathers) for every column
+    // group of the reduction, which would otherwise read them again from
+    // device memory
+    if (us != nullptr) {
+#pragma unroll
+      for (int h = 0; h < 4 / W; ++h)
+        *reinterpret_cast<VT*>(us + (r - r0) + h * W) = ld16<T>(u + r + h * W);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) o[i] = out[i];
     *reinterpret_cast<A4*>(zs + (r - r0)) = o;
@@ -1969,12 +1984,12 @@ __global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
   }
   __syncthreads();
   reduce_body<CPW, true, true, T, true>(gr, w, n, j, rows_per_block, cpw, wc, wr, nullptr, 0,
-                                        nullptr, nullptr, sm, zs);
+                                        nullptr, nullptr, sm, zs, us);
 }
 
 template <typename T>
 using OpReduceKernel = void (*)(Work, long long, int, long long, int, int, int, int, const int*,
-                                const T*);
+                                const T*, int);
 
 template <typename T>
 static OpReduceKernel<T> pick_opreduce(int tcpw) {
@@ -1987,8 +2002,25 @@ static OpReduceKernel<T> pick_opreduce(int tcpw) {
   }
 }
 
-// Largest share of a block's rows of z kept in shared memory (bytes).
+// Largest share of a block's rows of z kept in shared memory (bytes).  Its
+// rows of u are kept there too when both fit.
 constexpr size_t kFusedZBytes = 128 * 1024;
+
+// Dynamic shared memory a block may use on the current device (cached).
+static size_t max_lds_per_block() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> g(mu);
+  const auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v < 0)
+    v = 0;
+  cache[dev] = (size_t)v;
+  return (size_t)v;
+}
 
 // The launch of the fused kernel for iteration j, or nblocks = 0 when the
 // operator apply and the reduction must run as two kernels: no ELL form,
@@ -1999,6 +2031,7 @@ struct FusedLaunch {
   const void* kernel = nullptr;
   ReduceShape sh{};
   size_t lds = 0;
+  int u_lds = 0;
   int nblocks = 0;
 };
 
@@ -2031,11 +2064,15 @@ static FusedLaunch opreduce_plan(const Op& op, const Work& w, long long n, int j
   if (zbytes > kFusedZBytes) return f;
   const void* k = reinterpret_cast<const void*>(pick_opreduce<T>(sh.tcpw));
   if (k == nullptr) return f;
-  const size_t lds = zbytes + red_lds;
+  const size_t cap_lds = max_lds_per_block();
+  const int u_lds = (2 * zbytes + red_lds <= cap_lds) ? 1 : 0;
+  const size_t lds = (u_lds ? 2 : 1) * zbytes + red_lds;
+  if (lds > cap_lds) return f;
   if (resident_blocks(k, kReduceThreads, lds) < sh.nblocks) return f;
   f.kernel = k;
   f.sh = sh;
   f.lds = lds;
+  f.u_lds = u_lds;
   f.nblocks = sh.nblocks;
   return f;
 }
@@ -2056,7 +2093,8 @@ static hipError_t opreduce_launch(const Op& op, const Work& w, long long n, int 
   int ja = j, cpw = f.sh.cpw, wc = f.sh.wc, wr = f.sh.wr, k = op.ell_k;
   const int* col = op.ell_col;
   const T* val = ell_vals<T>(op);
-  void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &k, &col, &val};
+  int ul = f.u_lds;
+  void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &k, &col, &val, &ul};
   return hipLaunchKernel(f.kernel, dim3(f.nblocks), dim3(kReduceThreads), args, f.lds, s);
 }
 
