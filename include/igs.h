@@ -155,7 +155,10 @@ typedef struct igs_info {
   int lagnorm_fallbacks;    /* explicit-norm recomputations (gs_iters=2)        */
   int last_cycle_status;    /* IGS_CYCLE_* of the last cycle                     */
   int first_cycle_J;        /* columns finished in the first cycle              */
-  int reserved;
+  int stagnant_cycles;      /* restart cycles after which the true residual
+                               ||b - A x|| was above (1 - 1e-3) times its value
+                               at the cycle's start (a restarted solve that
+                               stalls shows a growing count)                  */
   double seconds;           /* wall time of the call                            */
 } igs_info;
 

@@ -659,6 +659,17 @@ extern "C" int igs_solve(igs_ctx* c, const double* b, double* x, int restart, do
 
 namespace {
 
+// A restart cycle counts as stagnant (igs_info.stagnant_cycles) when the true
+// residual ||b - A x|| at the start of the next cycle is above
+// (1 - kStagnationDrop) times its value at the cycle's own start.  A cycle
+// whose start or end residual is not finite is not counted.
+constexpr double kStagnationDrop = 1e-3;
+
+bool cycle_stagnated(double rho_start, double rho_next) {
+  return isfinite(rho_start) && isfinite(rho_next) && rho_start > 0.0 &&
+         rho_next > (1.0 - kStagnationDrop) * rho_start;
+}
+
 // Record the launches `enqueue` makes into the context's cycle graph.
 template <typename F>
 int record_cycle(igs_ctx* c, F&& enqueue) {
@@ -762,6 +773,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   int status = igs::kRunning;
   int ret = IGS_ENOCONV;
   double relres = NAN, arn = NAN;
+  double rho_prev = NAN;   // ||b - A x|| at the start of the previous cycle
+  int stagnant = 0;
   bool converged = false;
   bool final_check = false;
   int cycles_timed = 0;   // the cycle index the profiling events carry
@@ -926,6 +939,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     }
     cycles += 1;
     relres = bnorm > 0 ? h.rho / bnorm : h.rho;
+    if (cycle_stagnated(rho_prev, h.rho)) stagnant += 1;
+    rho_prev = h.rho;
     if (status == igs::kConvStart) {
       converged = true;
       ret = IGS_OK;
@@ -957,6 +972,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     info->converged = converged ? 1 : 0;
     info->breakdowns = c->h_ctl->breakdowns;
     info->lagnorm_fallbacks = c->h_ctl->fallbacks;
+    info->stagnant_cycles = stagnant;
     info->last_cycle_status = status;
     info->first_cycle_J = c->J_first;
     info->seconds =
@@ -1507,7 +1523,8 @@ struct Member {
   int rc = IGS_ENOCONV;
   int status = igs::kRunning;
   double bnorm = 0.0, relres = NAN, arn = NAN;
-  int breakdowns = 0, fallbacks = 0, J_first = -1;
+  double rho_prev = NAN;       // ||b - A x|| at the start of the previous cycle
+  int breakdowns = 0, fallbacks = 0, J_first = -1, stagnant = 0;
 };
 
 struct Batch {
@@ -1705,6 +1722,8 @@ int batch_cycle(Batch& B, const BatchParams& p) {
     if (M.cycles == 0 && !M.final_check) M.J_first = J;
     M.cycles += 1;
     M.relres = M.bnorm > 0 ? h.rho / M.bnorm : h.rho;
+    if (cycle_stagnated(M.rho_prev, h.rho)) M.stagnant += 1;
+    M.rho_prev = h.rho;
     if (M.status == igs::kConvStart) {
       M.converged = true;
       M.rc = IGS_OK;
@@ -1744,7 +1763,7 @@ void member_info(const Member& M, igs_info* info, double seconds) {
   info->lagnorm_fallbacks = M.fallbacks;
   info->last_cycle_status = M.status;
   info->first_cycle_J = M.J_first;
-  info->reserved = 0;
+  info->stagnant_cycles = M.stagnant;
   info->seconds = seconds;
 }
 

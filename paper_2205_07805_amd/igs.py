@@ -48,7 +48,7 @@ class IgsInfo(ctypes.Structure):
     _fields_ = [("iters", c_int64), ("cycles", c_int64), ("relres_true", c_double),
                 ("arnoldi_relres", c_double), ("bnorm", c_double), ("converged", c_int),
                 ("breakdowns", c_int), ("lagnorm_fallbacks", c_int), ("last_cycle_status", c_int),
-                ("first_cycle_J", c_int), ("reserved", c_int), ("seconds", c_double)]
+                ("first_cycle_J", c_int), ("stagnant_cycles", c_int), ("seconds", c_double)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

@@ -404,3 +404,47 @@ def test_longest_restart_dense_1000(torch):
     r_gpu = np.linalg.norm(b - op.matvec(x))
     r_ref = np.linalg.norm(b - op.matvec(ref.x))
     assert abs(r_gpu - r_ref) <= 1e-10 * np.linalg.norm(b)
+
+
+def cyclic_shift(n):
+    """The cyclic shift A e_i = e_{i+1 mod n} in CSR: with b = e_0 the Krylov
+    space of GMRES(m), m < n, is span(e_0 .. e_{m-1}) and A maps it onto
+    span(e_1 .. e_m), orthogonal to b, so the least-squares solution is zero
+    and a restart cycle leaves the residual exactly where it was."""
+    row_ptr = np.arange(n + 1, dtype=np.int32)
+    col_idx = np.array([n - 1] + list(range(n - 1)), dtype=np.int32)
+    return W.Csr(n, row_ptr, col_idx, np.ones(n))
+
+
+def test_stagnation_is_reported(torch):
+    """igs_info.stagnant_cycles counts the full cycles after which the true
+    residual fell by less than 1e-3 of its value: every cycle on the cyclic
+    shift (the oracle makes no progress either), none on a converging solve;
+    the lone and the batched drivers agree."""
+    from paper_2205_07805_amd import Solver, igs, solve_batch
+    n, m, cycles = 64, 10, 3
+    a = cyclic_shift(n)
+    b = np.zeros(n)
+    b[0] = 1.0
+    ref = O.gmres(a, b, restart=m, tol=1e-12, variant="igs1r", maxit=cycles * m)
+    assert ref.status == "maxit" and ref.relres_true == 1.0
+    print("stagnation: cyclic shift, lone", flush=True)
+    x, rc, info, _, _ = gpu(a, b, m, 1e-12, 2, maxit=cycles * m)
+    assert rc == igs.IGS_ENOCONV and info["iters"] == ref.iters == cycles * m
+    assert info["relres_true"] == 1.0 and np.all(x == 0.0)
+    assert info["stagnant_cycles"] == cycles
+    c2, b2 = W.make_convdiff2d_32()
+    _, rc2, info2, _, _ = gpu(c2, b2, 50, 1e-12, 2)
+    assert rc2 == 0 and info2["cycles"] >= 2 and info2["stagnant_cycles"] == 0
+    print("stagnation: batched", flush=True)
+    solvers = [Solver(a), Solver(c2)]
+    try:
+        xs, rcb, infos, rcs = solve_batch(solvers, [b, b2], restart=m, tol=1e-12, maxit=cycles * m)
+        assert rcs[0] == igs.IGS_ENOCONV and infos[0]["stagnant_cycles"] == cycles
+        assert infos[0]["iters"] == cycles * m
+        # the 2D system does not converge in 3 cycles of 10, but each cycle
+        # lowers its residual by far more than 1e-3
+        assert rcs[1] == igs.IGS_ENOCONV and infos[1]["stagnant_cycles"] == 0
+    finally:
+        for s in solvers:
+            s.close()
