@@ -2192,7 +2192,9 @@ __host__ __device__ __forceinline__ size_t update_lds_doubles(int j) {
 // Rows of one tile of the update: every thread owns NV 16-byte row vectors
 // (2 NV rows of doubles or 4 NV of floats), so a block reads each column of V
 // in runs of NV x 4 KB.  Longer runs per column stream faster from HBM (about
-// 6.2 TB/s with 8 KB runs against 6.8 with 16 KB on the 2M-row basis).
+// 6.2 TB/s with 8 KB runs against 6.8 with 16 KB on the 2M-row basis; with
+// 32 KB runs and the column loads pipelined, the 2M-row update takes 85.7
+// against 91.1 us).
 template <typename T, int NV = 2>
 __host__ __device__ constexpr long long update_tile_rows() {
   return (long long)NV * Vec16<T>::W * kUpdateThreads;
@@ -2410,6 +2412,31 @@ __device__ __forceinline__ void update_body(
           }
         };
         int c = 0;
+        if constexpr (NV >= 8) {
+          // Two register stages of one column each, alternating roles: the
+          // next column's loads are issued before the FMAs of the current
+          // one (without a next column the current one is loaded again and
+          // not used, so the loads stay unconditional).
+          auto load = [&](VT* v, int cb) {
+            const T* vc = V + (size_t)cb * ldv;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] = ld16_stream<T>(vc + p[k]);
+          };
+          if (j >= 1) {
+            VT va[NV], vb[NV];
+            load(va, 0);
+            while (true) {
+              load(vb, (c + 1 < j) ? c + 1 : c);
+              use(va, c);
+              ++c;
+              if (c >= j) break;
+              load(va, (c + 1 < j) ? c + 1 : c);
+              use(vb, c);
+              ++c;
+              if (c >= j) break;
+            }
+          }
+        }
         for (; c + CB <= j; c += CB) {
           VT v[CB][NV];
 #pragma unroll
@@ -2630,13 +2657,16 @@ template <typename T>
 using UpdateKernel = void (*)(Work, long long, int, int, T*, long long, const T*, const double*,
                               const double*, double, int);
 
-// Row vectors per thread of the single-instance update: the largest of 4, 2
+// Row vectors per thread of the single-instance update: the largest of 8
+// (FP64 only: the FP32 accumulators would not leave two blocks per CU), 4, 2
 // and 1 whose tiles still number at least one per CU; 0 (the column split)
 // when the solve allows it and even one vector per thread gives fewer tiles
 // than half the CUs.
 template <typename T>
 static int update_nv(long long n, bool col_split) {
   const long long cus = resident_blocks(nullptr, 0, 0);
+  if (sizeof(T) == 8 && (n + update_tile_rows<T, 8>() - 1) / update_tile_rows<T, 8>() >= cus)
+    return 8;
   if ((n + update_tile_rows<T, 4>() - 1) / update_tile_rows<T, 4>() >= cus) return 4;
   if ((n + update_tile_rows<T, 2>() - 1) / update_tile_rows<T, 2>() >= cus) return 2;
   if (!col_split || (n + update_tile_rows<T, 1>() - 1) / update_tile_rows<T, 1>() >= cus / 2)
@@ -2659,7 +2689,10 @@ static hipError_t update_dispatch(const Work& w, long long n, int j, bool has_t,
   const int nv = vec ? update_nv<T>(n, raw == 0 && w.col_split) : 2;
   UpdateKernel<T> k;
   long long tile_rows;
-  if (nv == 4) {
+  if (nv == 8) {
+    k = has_t ? update_kernel<true, true, T, 8> : update_kernel<false, true, T, 8>;
+    tile_rows = update_tile_rows<T, 8>();
+  } else if (nv == 4) {
     k = has_t ? update_kernel<true, true, T, 4> : update_kernel<false, true, T, 4>;
     tile_rows = update_tile_rows<T, 4>();
   } else if (nv == 1) {
