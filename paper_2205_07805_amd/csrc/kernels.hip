@@ -1907,36 +1907,36 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
 // with contraction off; the reduction then adds the same values in the same
 // order, so its sums are bit-identical too.
 
-// Four consecutive rows r .. r+3 of z = A x from the column-major ELL form
+// R consecutive rows r .. r+R-1 of z = A x from the column-major ELL form
 // (entry slot k of row r at k n + r; K <= 8 slots): each slot's column indices
-// and values are read as one vector of four.  Needs n and r multiples of 4
-// and 16-byte aligned arrays (32-byte for FP64 values).
-template <typename T>
-__device__ __forceinline__ void ell_rows4(const int* __restrict__ col, const T* __restrict__ val,
+// and values are read as one vector of R.  Needs n and r multiples of R and
+// arrays aligned to their vectors.
+template <typename T, int R>
+__device__ __forceinline__ void ell_rowsR(const int* __restrict__ col, const T* __restrict__ val,
                                           long long n, int K, const T* __restrict__ x,
                                           long long r, T* out) {
 #pragma clang fp contract(off)
-  typedef int I4 __attribute__((ext_vector_type(4)));
-  typedef T A4 __attribute__((ext_vector_type(4)));
-  I4 c[8];
-  A4 v[8];
+  typedef int IR __attribute__((ext_vector_type(R)));
+  typedef T AR __attribute__((ext_vector_type(R)));
+  IR c[8];
+  AR v[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (k < K) {
-      c[k] = *reinterpret_cast<const I4*>(col + (long long)k * n + r);
-      v[k] = *reinterpret_cast<const A4*>(val + (long long)k * n + r);
+      c[k] = *reinterpret_cast<const IR*>(col + (long long)k * n + r);
+      v[k] = *reinterpret_cast<const AR*>(val + (long long)k * n + r);
     } else {
-      c[k] = I4(0);
-      v[k] = A4(0);
+      c[k] = IR(0);
+      v[k] = AR(0);
     }
   }
-  T g[8][4];
+  T g[8][R];
 #pragma unroll
   for (int k = 0; k < 8; ++k)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) g[k][i] = x[c[k][i]];
+    for (int i = 0; i < R; ++i) g[k][i] = x[c[k][i]];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < R; ++i) {
     T p[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) p[k] = v[k][i] * g[k][i];
@@ -1952,7 +1952,6 @@ __global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
     const int* __restrict__ ell_col, const T* __restrict__ ell_val, int u_lds) {
   extern __shared__ double lds[];
   if (!ctl_runs(w.ctl, j)) return;
-  typedef T A4 __attribute__((ext_vector_type(4)));
   const Grid gr = hw_grid();
   const long long r0 = (long long)gr.bid * rows_per_block;
   const long long r1 = min(n, r0 + rows_per_block);
@@ -1965,22 +1964,20 @@ __global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
   T* __restrict__ zg = zvec<T>(w);
   typedef typename Vec16<T>::type VT;
   constexpr int W = Vec16<T>::W;
-  for (long long r = r0 + 4 * (long long)threadIdx.x; r < r1; r += 4LL * kReduceThreads) {
-    A4 o;
-    T out[4];
-    ell_rows4<T>(ell_col, ell_val, n, ell_k, u, r, out);
+  // W rows per thread and step (one 16-byte vector of each entry slot's
+  // values: two rows of doubles, four of floats)
+  for (long long r = r0 + W * (long long)threadIdx.x; r < r1; r += (long long)W * kReduceThreads) {
+    VT o;
+    T out[W];
+    ell_rowsR<T, W>(ell_col, ell_val, n, ell_k, u, r, out);
     // the block's own rows of u (also among the gathers) for every column
     // group of the reduction, which would otherwise read them again from
     // device memory
-    if (us != nullptr) {
+    if (us != nullptr) *reinterpret_cast<VT*>(us + (r - r0)) = ld16<T>(u + r);
 #pragma unroll
-      for (int h = 0; h < 4 / W; ++h)
-        *reinterpret_cast<VT*>(us + (r - r0) + h * W) = ld16<T>(u + r + h * W);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = out[i];
-    *reinterpret_cast<A4*>(zs + (r - r0)) = o;
-    __builtin_nontemporal_store(o, reinterpret_cast<A4*>(zg + r));   // see st16
+    for (int i = 0; i < W; ++i) o[i] = out[i];
+    *reinterpret_cast<VT*>(zs + (r - r0)) = o;
+    __builtin_nontemporal_store(o, reinterpret_cast<VT*>(zg + r));   // see st16
   }
   __syncthreads();
   reduce_body<CPW, true, true, T, true>(gr, w, n, j, rows_per_block, cpw, wc, wr, nullptr, 0,
