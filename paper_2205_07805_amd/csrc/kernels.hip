@@ -1909,15 +1909,18 @@ hipError_t launch_reduce_raw(const double* V, long long ldv, long long n, int j,
 
 // R consecutive rows r .. r+R-1 of z = A x from the column-major ELL form
 // (entry slot k of row r at k n + r; K <= 8 slots): each slot's column indices
-// and values are read as one vector of R.  Needs n and r multiples of R and
-// arrays aligned to their vectors.
-template <typename T, int R>
-__device__ __forceinline__ void ell_rowsR(const int* __restrict__ col, const T* __restrict__ val,
+// and values are read as one vector of R.  D16: the indices are 16-bit
+// offsets from the row (col - r), padding 0.  Needs n and r multiples of R
+// and arrays aligned to their vectors.
+template <typename T, int R, bool D16>
+__device__ __forceinline__ void ell_rowsR(const void* __restrict__ idx, const T* __restrict__ val,
                                           long long n, int K, const T* __restrict__ x,
                                           long long r, T* out) {
 #pragma clang fp contract(off)
-  typedef int IR __attribute__((ext_vector_type(R)));
+  typedef typename std::conditional<D16, short, int>::type I;
+  typedef I IR __attribute__((ext_vector_type(R)));
   typedef T AR __attribute__((ext_vector_type(R)));
+  const I* __restrict__ col = static_cast<const I*>(idx);
   IR c[8];
   AR v[8];
 #pragma unroll
@@ -1934,7 +1937,8 @@ __device__ __forceinline__ void ell_rowsR(const int* __restrict__ col, const T* 
 #pragma unroll
   for (int k = 0; k < 8; ++k)
 #pragma unroll
-    for (int i = 0; i < R; ++i) g[k][i] = x[c[k][i]];
+    for (int i = 0; i < R; ++i)
+      g[k][i] = D16 ? x[r + i + (long long)c[k][i]] : x[(long long)c[k][i]];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     T p[8];
@@ -1946,10 +1950,10 @@ __device__ __forceinline__ void ell_rowsR(const int* __restrict__ col, const T* 
   }
 }
 
-template <int CPW, typename T>
+template <int CPW, typename T, bool D16>
 __global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
     Work w, long long n, int j, long long rows_per_block, int cpw, int wc, int wr, int ell_k,
-    const int* __restrict__ ell_col, const T* __restrict__ ell_val, int u_lds) {
+    const void* __restrict__ ell_idx, const T* __restrict__ ell_val, int u_lds) {
   extern __shared__ double lds[];
   if (!ctl_runs(w.ctl, j)) return;
   const Grid gr = hw_grid();
@@ -1969,7 +1973,7 @@ __global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
   for (long long r = r0 + W * (long long)threadIdx.x; r < r1; r += (long long)W * kReduceThreads) {
     VT o;
     T out[W];
-    ell_rowsR<T, W>(ell_col, ell_val, n, ell_k, u, r, out);
+    ell_rowsR<T, W, D16>(ell_idx, ell_val, n, ell_k, u, r, out);
     // the block's own rows of u (also among the gathers) for every column
     // group of the reduction, which would otherwise read them again from
     // device memory
@@ -1985,16 +1989,20 @@ __global__ __launch_bounds__(kReduceThreads) void opreduce_kernel(
 }
 
 template <typename T>
-using OpReduceKernel = void (*)(Work, long long, int, long long, int, int, int, int, const int*,
+using OpReduceKernel = void (*)(Work, long long, int, long long, int, int, int, int, const void*,
                                 const T*, int);
 
 template <typename T>
-static OpReduceKernel<T> pick_opreduce(int tcpw) {
-  switch (tcpw) {
-    case 1: return opreduce_kernel<1, T>;
-    case 2: return opreduce_kernel<2, T>;
-    case 4: return opreduce_kernel<4, T>;
-    case 8: return opreduce_kernel<8, T>;
+static OpReduceKernel<T> pick_opreduce(int tcpw, bool d16) {
+  switch (tcpw * 2 + (d16 ? 1 : 0)) {
+    case 2: return opreduce_kernel<1, T, false>;
+    case 3: return opreduce_kernel<1, T, true>;
+    case 4: return opreduce_kernel<2, T, false>;
+    case 5: return opreduce_kernel<2, T, true>;
+    case 8: return opreduce_kernel<4, T, false>;
+    case 9: return opreduce_kernel<4, T, true>;
+    case 16: return opreduce_kernel<8, T, false>;
+    case 17: return opreduce_kernel<8, T, true>;
     default: return nullptr;
   }
 }
@@ -2029,6 +2037,7 @@ struct FusedLaunch {
   ReduceShape sh{};
   size_t lds = 0;
   int u_lds = 0;
+  const void* idx = nullptr;   // ELL column indices: 32-bit, or 16-bit offsets
   int nblocks = 0;
 };
 
@@ -2044,6 +2053,8 @@ static FusedLaunch opreduce_plan(const Op& op, const Work& w, long long n, int j
       reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T)) != 0 ||
       reinterpret_cast<uintptr_t>(V) % 16 != 0 || w.ldv % Vec16<T>::W != 0)
     return f;
+  // the column indices as 16-bit offsets from the row where they exist
+  const bool d16 = op.ell_dcol != nullptr && reinterpret_cast<uintptr_t>(op.ell_dcol) % 16 == 0;
   const int ncol = j + 1;
   ReduceShape sh = reduce_shape(j);
   const size_t red_lds = reduce_lds_bytes(sh, ncol);
@@ -2059,7 +2070,7 @@ static FusedLaunch opreduce_plan(const Op& op, const Work& w, long long n, int j
   reduce_rows(sh, n, cap);
   const size_t zbytes = (size_t)sh.rows_per_block * sizeof(T);
   if (zbytes > kFusedZBytes) return f;
-  const void* k = reinterpret_cast<const void*>(pick_opreduce<T>(sh.tcpw));
+  const void* k = reinterpret_cast<const void*>(pick_opreduce<T>(sh.tcpw, d16));
   if (k == nullptr) return f;
   const size_t cap_lds = max_lds_per_block();
   const int u_lds = (2 * zbytes + red_lds <= cap_lds) ? 1 : 0;
@@ -2070,6 +2081,7 @@ static FusedLaunch opreduce_plan(const Op& op, const Work& w, long long n, int j
   f.sh = sh;
   f.lds = lds;
   f.u_lds = u_lds;
+  f.idx = d16 ? static_cast<const void*>(op.ell_dcol) : static_cast<const void*>(op.ell_col);
   f.nblocks = sh.nblocks;
   return f;
 }
@@ -2088,10 +2100,10 @@ static hipError_t opreduce_launch(const Op& op, const Work& w, long long n, int 
   Work wa = w;
   long long na = n, rpb = f.sh.rows_per_block;
   int ja = j, cpw = f.sh.cpw, wc = f.sh.wc, wr = f.sh.wr, k = op.ell_k;
-  const int* col = op.ell_col;
+  const void* idx = f.idx;
   const T* val = ell_vals<T>(op);
   int ul = f.u_lds;
-  void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &k, &col, &val, &ul};
+  void* args[] = {&wa, &na, &ja, &rpb, &cpw, &wc, &wr, &k, &idx, &val, &ul};
   return hipLaunchKernel(f.kernel, dim3(f.nblocks), dim3(kReduceThreads), args, f.lds, s);
 }
 

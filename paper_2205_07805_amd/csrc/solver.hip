@@ -83,6 +83,7 @@ struct igs_ctx {
   double* d_A = nullptr;
   float* d_vals32 = nullptr;   // CSR values rounded to FP32 (first mixed-precision solve)
   int* d_ell_col = nullptr;    // the operator in column-major ELL form (short rows)
+  short* d_ell_dcol = nullptr; // its column indices as 16-bit offsets from the row
   double* d_ell_val = nullptr;
   float* d_ell_val32 = nullptr;
   long long n_cap = 0, nnz_cap = 0;  // serving slot: device capacity for rebinding operators
@@ -574,6 +575,27 @@ extern "C" int igs_create(igs_ctx** out, int64_t n, int64_t nnz, const int32_t* 
       c->op.ell_k = (int)kmax;
       c->op.ell_col = c->d_ell_col;
       c->op.ell_val = c->d_ell_val;
+      // the same indices as offsets from the row, when all fit 16 bits
+      bool narrow = true;
+      for (long long i = 0; i < n && narrow; ++i)
+        for (long long k = rp[i]; k < rp[i + 1]; ++k)
+          if (ci[k] - i > 32767 || ci[k] - i < -32767) {
+            narrow = false;
+            break;
+          }
+      if (narrow) {
+        std::vector<int16_t> ed((size_t)kmax * n, 0);
+        for (long long i = 0; i < n; ++i)
+          for (long long k = rp[i]; k < rp[i + 1]; ++k)
+            ed[(size_t)(k - rp[i]) * n + i] = (int16_t)(ci[k] - i);
+        if (dalloc(&c->d_ell_dcol, (size_t)kmax * n) != hipSuccess ||
+            hipMemcpy(c->d_ell_dcol, ed.data(), sizeof(int16_t) * kmax * n,
+                      hipMemcpyHostToDevice) != hipSuccess) {
+          set_err(c, IGS_ENOMEM, "device allocation of the ELL offsets failed");
+          return fail_create(c, IGS_ENOMEM);
+        }
+        c->op.ell_dcol = c->d_ell_dcol;
+      }
     }
   }
   *out = c;
@@ -638,7 +660,7 @@ extern "C" int igs_destroy(igs_ctx* c) {
   free_workspace(c);
   free_raw(c);
   void* ptrs[] = {c->d_row_ptr, c->d_col, c->d_vals, c->d_A, c->d_vals32, c->d_ell_col,
-                  c->d_ell_val, c->d_ell_val32};
+                  c->d_ell_val, c->d_ell_val32, c->d_ell_dcol};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -1355,6 +1377,7 @@ int slot_bind(igs_ctx* c, long long n, long long nnz, const int32_t* rp, const i
   c->op.ell_col = nullptr;
   c->op.ell_val = nullptr;
   c->op.ell_val32 = nullptr;
+  c->op.ell_dcol = nullptr;
   if (lpr == 8 && kmax >= 1 && kmax <= 8 && c->d_ell_col && c->d_ell_val) {
     HIP_OR_FAIL(c, igs::launch_csr_to_ell(n, (int)kmax, c->d_row_ptr, c->d_col, c->d_vals,
                                           c->d_ell_col, c->d_ell_val, c->stream));

@@ -3,9 +3,12 @@ reduction takes A u as an operand) against the operator apply and the
 reduction as two kernels (opts.separate_apply), through the C ABI.
 
 Every row of z has the separate kernels' products and additions in their
-order, and the reduction then adds the same values in the same order on the
-same grid, so whole solves must agree bit for bit: x, the first cycle's
-Hessenberg matrix and the iteration count.  A per-kernel profile shows which
+order (the fused kernel reads the column indices as 16-bit offsets from the
+row where every entry lies within 32,767 columns of its row, padding then
+multiplying x[r] by zero instead of x[0]), and the reduction then adds the
+same values in the same order on the same grid, so whole solves must agree
+bit for bit: x, the first cycle's Hessenberg matrix and the iteration
+count.  A per-kernel profile shows which
 path ran.  Systems whose row count is not a multiple of 4 take the two
 kernels; that path is checked the same way.  The oracle's first cycle and x
 are checked beside it."""
@@ -38,7 +41,29 @@ def run(a, b, restart, tol, gs, **opts):
         s.close()
 
 
+def banded(n, far, seed=5):
+    """Rows with entries at offsets -far, -2, -1, 0, 1, 2, far (where in
+    range), diagonally dominant and non-symmetric: 7 ELL slots whose column
+    offsets reach `far`.  The fused kernel reads the indices as 16-bit
+    offsets from the row when far <= 32,767, else as 32-bit columns."""
+    rng = np.random.default_rng(seed)
+    offs = (-far, -2, -1, 0, 1, 2, far)
+    row_ptr, cols, vals = [0], [], []
+    for r in range(n):
+        for o in offs:
+            c = r + o
+            if 0 <= c < n:
+                cols.append(c)
+                vals.append(8.0 + rng.uniform() if o == 0 else -rng.uniform(0.2, 1.0))
+        row_ptr.append(len(cols))
+    return W.Csr(n, np.array(row_ptr, dtype=np.int32), np.array(cols, dtype=np.int32),
+                 np.array(vals))
+
+
 CASES = {
+    # column offsets at the 16-bit limit, and one past it (32-bit indices)
+    "banded_far32767": (lambda: banded(80_000, 32_767), 30, 1e-12, 0),
+    "banded_far32768": (lambda: banded(80_000, 32_768), 30, 1e-12, 0),
     # n = 1,024: a 5-slot ELL form, 4 reduction blocks
     "convdiff2d_32": (lambda: W.convdiff2d(32, 10.0), 50, 1e-12, 0),
     # n = 46,656: 7 slots, many blocks of 256 rows
@@ -75,7 +100,13 @@ def test_fused_apply_matches_separate_kernels_bit_for_bit(torch, case, gs):
     if not fp32:
         ref = O.gmres(a, b, restart=restart, tol=tol, variant=v, gs_iters=g, max_cycles=1)
         Hr = ref.first_cycle.H
-        for c in range(10):
+        # One sweep leaves errors of about eps / (Arnoldi residual) in a
+        # column (two sweeps do not): on a fast-converging system its late
+        # columns differ from any other rounding of the same method by more
+        # than 1e-11, so one sweep is held to the columns whose Arnoldi
+        # residual is still above 1e-4.
+        ncols = 10 if gs == 2 else max(3, min(10, int(np.sum(np.array(ref.res_hist) >= 1e-4))))
+        for c in range(ncols):
             nrm = np.linalg.norm(Hr[: c + 2, c])
             assert np.linalg.norm(H1[: c + 2, c] - Hr[: c + 2, c]) <= 1e-11 * nrm, c
     op = O.as_operator(a)
@@ -90,9 +121,9 @@ def test_fused_apply_at_full_size_first_cycle_bit_for_bit(torch):
     print(f"fused vs separate full size n={a.n}", flush=True)
     x1, rc1, i1, H1, p1 = run(a, b, 60, 1e-10, 2, max_cycles=1)
     x2, rc2, i2, H2, p2 = run(a, b, 60, 1e-10, 2, max_cycles=1, separate_apply=1)
-    # (the iterations whose separate reduction would run two blocks per CU,
-    # j = 2 and 3 with 4-column groups, take the two kernels: the fused
-    # kernel holds one block per CU and keeps the separate grid)
+    # (an iteration whose separate grid the fused kernel could not hold
+    # resident would take the two kernels; with two rows of doubles per
+    # thread in the operator apply it holds every one of them here)
     assert p1["opreduce"][0] >= 55 and p1["spmv"][0] <= 2, p1
     assert i1["first_cycle_J"] == i2["first_cycle_J"] == 60
     assert np.array_equal(H1, H2)
