@@ -101,7 +101,8 @@ typedef struct igs_opts {
                            of at most 8 entries) and n a multiple of 4, each
                            block of the reduction forms its own rows of A u
                            first (one launch and one read of u and of A u
-                           less per iteration); the results are
+                           less per iteration, the ELL columns read as 16-bit
+                           offsets where they fit); the results are
                            bit-identical either way.                        */
   double inner_rtol;    /* inner_fp32: a cycle also ends once its Arnoldi
                            residual is <= inner_rtol * ||r0|| of the cycle;
@@ -168,7 +169,13 @@ typedef struct igs_info {
  *   col_idx: int32[nnz], each in [0, n).  vals: float64[nnz], finite.
  *   ptrs_on_device: 0 = the three arrays are host memory, 1 = device memory.
  *   hip_stream: hipStream_t for all work of this context (NULL: null stream).
- * The arrays are validated and copied; the caller keeps ownership.
+ * The arrays are validated and copied; the caller keeps ownership.  When
+ * every row has at most 8 entries (and the mean row length is above 4), the
+ * context also keeps a column-major ELL copy (K x n values and int32
+ * columns, K the longest row) and, when every entry lies within 32,767
+ * columns of its row, the ELL columns as int16 offsets from the row: 12
+ * bytes per ELL slot, 2 more for the offsets (and 4 for FP32 values once a
+ * solve runs FP32 cycles), beside the CSR arrays.
  * Errors: IGS_EINVAL (n < 1, nnz < 0, malformed CSR, non-finite values),
  *         IGS_ENOMEM, IGS_EDEVICE.  On error *out is set to NULL.
  */
