@@ -130,6 +130,22 @@ def test_fused_apply_at_full_size_first_cycle_bit_for_bit(torch):
     assert np.array_equal(x1, x2)
 
 
+def test_fused_apply_without_u_in_shared_memory_bit_for_bit(torch):
+    """140^3 = 2,744,000 rows: a block's 10,752 rows of z (86 KB) fit its
+    shared memory but its rows of u would not fit beside them, so the fused
+    kernel reads u from device memory; one cycle of GMRES(20) fused and one
+    with two kernels, bit for bit."""
+    a = W.convdiff3d(140, 50.0)
+    b = W.rhs_normal(a.n, 1)
+    print(f"fused vs separate, u from device memory, n={a.n}", flush=True)
+    x1, rc1, i1, H1, p1 = run(a, b, 20, 1e-10, 2, max_cycles=1)
+    x2, rc2, i2, H2, p2 = run(a, b, 20, 1e-10, 2, max_cycles=1, separate_apply=1)
+    assert p1["opreduce"][0] >= 15, p1
+    assert i1["first_cycle_J"] == i2["first_cycle_J"] == 20
+    assert np.array_equal(H1, H2)
+    assert np.array_equal(x1, x2)
+
+
 @pytest.mark.parametrize("gs", [2, 1])
 @pytest.mark.parametrize("case", ["dense_nonnormal_1000_m150", "convdiff2d_40_m120"])
 def test_small_products_kernel_matches_update_blocks_bit_for_bit(torch, case, gs):
