@@ -197,9 +197,11 @@ def test_reduce_repeated_calls_agree_bit_for_bit(torch, n, j):
         assert np.array_equal(P, P0) and np.array_equal(Q, Q0), rep
 
 
+# n = 1,050,001 with an even leading dimension takes eight row vectors of
+# doubles per thread (257 tiles of 4,096 rows, the last one ragged)
 @pytest.mark.parametrize("pad", [3, 64], ids=["ld_odd", "ld_even"])
 @pytest.mark.parametrize("j", [0, 1, 7, 33, 60])
-@pytest.mark.parametrize("n", [100_003, 1_025, 4_096, 300_001, 600_001])
+@pytest.mark.parametrize("n", [100_003, 1_025, 4_096, 300_001, 600_001, 1_050_001])
 def test_update_matches_oracle(torch, n, j, pad):
     from paper_2205_07805_amd import igs
     print(f"update n={n} j={j} ldv=n+{pad}", flush=True)
