@@ -2809,12 +2809,92 @@ hipError_t launch_lsq(const Work& w, int m, hipStream_t s) {
   return hipGetLastError();
 }
 
-// x += V_{0:J} y (x and y FP64; V in the basis element type T).
-template <typename T>
+// x += V_{0:J} y (x and y FP64; V in the basis element type T), each row's
+// products added in column order and then to x.  NV > 0: tiles of NV
+// 16-byte row vectors per thread (runs of NV x 4 KB per column and block, as
+// the update takes them), the column loads in two alternating register
+// stages; rows past the last whole tile, or arrays the vectors cannot take,
+// one row per thread.  NV = 0: tiles of kUpdateRows rows per thread, element
+// loads.
+template <typename T, int NV>
+__device__ __forceinline__ void xupdate_vec(Grid gr, const Work& w, long long n,
+                                            double* __restrict__ x, int J) {
+  typedef typename Vec16<T>::type VT;
+  constexpr int W = Vec16<T>::W;
+  constexpr long long kTile = (long long)NV * W * kUpdateThreads;
+  const double* __restrict__ y = w.y;
+  const T* __restrict__ V = basis<T>(w);
+  const long long ntiles = (n + kTile - 1) / kTile;
+  for (long long tile = gr.bid; tile < ntiles; tile += gr.nb) {
+    const long long tb = tile * kTile;
+    if (tb + kTile <= n) {
+      long long p[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        p[k] = tb + (long long)W * threadIdx.x + (long long)k * W * kUpdateThreads;
+      double acc[NV][W];
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc[k][e] = 0.0;
+      auto load = [&](VT* v, int c) {
+        const T* vc = V + (size_t)c * w.ldv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = ld16_stream<T>(vc + p[k]);
+      };
+      auto use = [&](const VT* v, int c) {
+        const double yc = y[c];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+          for (int e = 0; e < W; ++e) acc[k][e] = fma((double)v[k][e], yc, acc[k][e]);
+      };
+      VT va[NV], vb[NV];
+      int c = 0;
+      load(va, 0);
+      while (true) {
+        load(vb, (c + 1 < J) ? c + 1 : c);
+        use(va, c);
+        if (++c >= J) break;
+        load(va, (c + 1 < J) ? c + 1 : c);
+        use(vb, c);
+        if (++c >= J) break;
+      }
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int h = 0; h < W; h += 2) {
+          double2 xv = *reinterpret_cast<const double2*>(x + p[k] + h);
+          xv.x += acc[k][h];
+          xv.y += acc[k][h + 1];
+          *reinterpret_cast<double2*>(x + p[k] + h) = xv;
+        }
+      continue;
+    }
+    // the ragged last tile: one row per thread
+    const long long te = min(n, tb + kTile);
+    for (long long r = tb + threadIdx.x; r < te; r += kUpdateThreads) {
+      double acc = 0.0;
+      for (int c = 0; c < J; ++c) acc = fma((double)V[(size_t)c * w.ldv + r], y[c], acc);
+      x[r] += acc;
+    }
+  }
+}
+
+template <typename T, int NV>
 __device__ __forceinline__ void xupdate_body(Grid gr, const Work& w, long long n,
                                              double* __restrict__ x) {
   const int J = load_agent(&w.ctl->J);
   if (J <= 0) return;
+  if constexpr (NV > 0) {
+    const bool vec = (w.ldv % Vec16<T>::W == 0) &&
+                     (reinterpret_cast<uintptr_t>(basis<T>(w)) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(x) % 16 == 0);
+    if (vec) {
+      xupdate_vec<T, NV>(gr, w, n, x, J);
+      return;
+    }
+  }
   const double* __restrict__ y = w.y;
   const T* __restrict__ V = basis<T>(w);
   constexpr long long kTile = (long long)kUpdateThreads * kUpdateRows;
@@ -2859,23 +2939,45 @@ __device__ __forceinline__ void xupdate_body(Grid gr, const Work& w, long long n
   }
 }
 
-template <typename T>
+template <typename T, int NV>
 __global__ __launch_bounds__(kUpdateThreads) void xupdate_kernel(Work w, long long n,
                                                                 double* __restrict__ x) {
-  xupdate_body<T>(hw_grid(), w, n, x);
+  xupdate_body<T, NV>(hw_grid(), w, n, x);
+}
+
+// One tile per block: eight row vectors of doubles (four of floats) per
+// thread when that still gives every CU a tile, else four, else element
+// loads with kUpdateRows rows per thread.
+template <typename T>
+static hipError_t xupdate_dispatch(const Work& w, long long n, double* x, hipStream_t s) {
+  const long long cus = resident_blocks(nullptr, 0, 0);
+  constexpr int W = Vec16<T>::W;
+  const long long t8 = (n + 8LL * W * kUpdateThreads - 1) / (8LL * W * kUpdateThreads);
+  const long long t4 = (n + 4LL * W * kUpdateThreads - 1) / (4LL * W * kUpdateThreads);
+  const void* k;
+  long long g;
+  if (sizeof(T) == 8 && t8 >= cus) {
+    k = reinterpret_cast<const void*>(xupdate_kernel<T, 8>);
+    g = t8;
+  } else if (t4 >= cus) {
+    k = reinterpret_cast<const void*>(xupdate_kernel<T, 4>);
+    g = t4;
+  } else {
+    const long long per = (long long)kUpdateThreads * kUpdateRows;
+    k = reinterpret_cast<const void*>(xupdate_kernel<T, 0>);
+    g = (n + per - 1) / per;
+  }
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  Work wa = w;
+  long long na = n;
+  double* xa = x;
+  void* args[] = {&wa, &na, &xa};
+  return hipLaunchKernel(k, dim3((unsigned)g), dim3(kUpdateThreads), args, 0, s);
 }
 
 hipError_t launch_xupdate(const Work& w, long long n, double* x, hipStream_t s) {
-  const long long per = (long long)kUpdateThreads * kUpdateRows;
-  long long g = (n + per - 1) / per;
-  if (g > kMaxBlocks) g = kMaxBlocks;
-  if (w.fp32)
-    hipLaunchKernelGGL(xupdate_kernel<float>, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w, n,
-                       x);
-  else
-    hipLaunchKernelGGL(xupdate_kernel<double>, dim3((unsigned)g), dim3(kUpdateThreads), 0, s, w,
-                       n, x);
-  return hipGetLastError();
+  if (w.fp32) return xupdate_dispatch<float>(w, n, x, s);
+  return xupdate_dispatch<double>(w, n, x, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -3164,7 +3266,7 @@ __global__ __launch_bounds__(kUpdateThreads) void xupdate_batch_kernel(const Ins
   if (bid >= e.nblk) return;
   const Inst I = tab[e.inst];
   if (!I.run_lsq) return;
-  xupdate_body<T>(Grid{bid, e.nblk}, I.w, I.n, I.x);
+  xupdate_body<T, 0>(Grid{bid, e.nblk}, I.w, I.n, I.x);
 }
 
 __global__ void ctl_gather_kernel(const Inst* __restrict__ tab, BatchMap map, Ctl* out) {
