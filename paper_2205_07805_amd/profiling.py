@@ -64,9 +64,11 @@ def family(name: str) -> str | None:
     for key in ("spmv_csr_kernel", "spmv_ell_kernel", "gemv_dense_kernel", "gemv_mfma_kernel"):
         if key in s:
             return "spmv"
+    # (a name can hold another's: opreduce_kernel holds reduce_kernel and
+    # xupdate_kernel holds update_kernel, so the longer names come first)
     for key, fam in (("opreduce_kernel", "opreduce"), ("reduce_kernel", "reduce"),
-                     ("update_kernel", "update"), ("coef_kernel", "coef"),
-                     ("xupdate_kernel", "xupdate"), ("lsq_kernel", "lsq"),
+                     ("xupdate_kernel", "xupdate"), ("update_kernel", "update"),
+                     ("coef_kernel", "coef"), ("lsq_kernel", "lsq"),
                      ("cycle_begin_kernel", "cycle_begin"), ("bnorm_kernel", "bnorm")):
         if key in s:
             return fam
