@@ -107,17 +107,21 @@ def oracle_rate(a, b, restart, tol, n_iters, threads=None):
     return res.iters / dt, int(used), res.iters, dt
 
 
-def cpu_baseline(a, b, restart, tol, n_iters, n_iters_single):
+def cpu_baseline(a, b, restart, tol, n_iters, n_iters_single, bytes_per_iter=None):
     """The FP64 oracle on the host: the same solve, stopped after n_iters
     Arnoldi iterations on all the BLAS threads, and after n_iters_single on
-    one thread."""
+    one thread.  With bytes_per_iter (the GPU solve's algorithmic bytes per
+    iteration), also the oracle's algorithmic GB/s at the same count."""
     rate, used, its, dt = oracle_rate(a, b, restart, tol, n_iters)
     rate1, _, its1, dt1 = oracle_rate(a, b, restart, tol, n_iters_single, threads=1)
+    gbs = (lambda r: r * bytes_per_iter / 1e9 if bytes_per_iter else None)
     return {"value": rate, "unit": "Arnoldi iters/s", "cores": used, "kind": "oracle",
+            "algorithmic_GBs": gbs(rate),
             "sample": f"first {its} Arnoldi iterations ({its // restart} GMRES({restart}) "
                       f"cycles, one-reduce, two sweeps) of the same {a.n}-row solve, {dt:.1f} s "
                       f"on {used} BLAS threads",
             "single_thread": {"value": rate1, "unit": "Arnoldi iters/s", "cores": 1,
+                              "algorithmic_GBs": gbs(rate1),
                               "sample": f"first {its1} Arnoldi iterations, {dt1:.1f} s"},
             **host_cpu()}
 
@@ -450,7 +454,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(a, b, args.restart, args.tol, args.cpu_iters, args.cpu_iters_single)
+        cpu = cpu_baseline(a, b, args.restart, args.tol, args.cpu_iters, args.cpu_iters_single,
+                           bytes_per_iter=(total_bytes / iters) if total_bytes and iters else None)
         log(f"[bench] cpu baseline: {cpu['value']:.2f} iters/s on {cpu['cores']} threads, "
             f"{cpu['single_thread']['value']:.2f} on one ({cpu['cpu_model']})")
 
