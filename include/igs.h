@@ -147,7 +147,10 @@ typedef struct igs_opts {
 /* Result summary of a solve.  Any pointer argument of this type may be NULL. */
 typedef struct igs_info {
   int64_t iters;            /* Arnoldi iterations = sum of finished columns     */
-  int64_t cycles;           /* restart cycles run (incl. the final check)       */
+  int64_t cycles;           /* restart cycles run, incl. check cycles (the
+                               explicit residual and iteration 0 only: after
+                               the iteration budget, and after a cycle that
+                               met the tolerance by its Arnoldi residual)     */
   double relres_true;       /* ||b - A x|| / ||b|| at the last explicit residual */
   double arnoldi_relres;    /* |g_J| / ||b|| at the end of the last full cycle  */
   double bnorm;             /* ||b||                                            */

@@ -902,11 +902,19 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
   key.maxit = maxit;
   key.fuse = fuse ? 1 : 0;
   key.pre = w.pre_on;
+  // After a cycle whose Arnoldi residual met the tolerance, the next cycle
+  // is a check cycle too (its residual and iteration 0 only): the true
+  // residual nearly always confirms convergence there, and a full cycle's
+  // remaining launches would only return at once.  If it does not, a full
+  // cycle follows.
+  bool probe = false;
+  bool skip_stagnation = false;   // a full cycle after a failed probe starts where the probe did
   while (true) {
     const long long its_before = its;
-    const long long maxit_cycle = final_check ? its : maxit;  // a check cycle runs iteration 0 only
+    const bool check = final_check || probe;
+    const long long maxit_cycle = check ? its : maxit;  // a check cycle runs iteration 0 only
     cycles_timed = cycles;
-    if (graph_ok && !final_check) {
+    if (graph_ok && !check) {
       if (!c->cycle_exec || memcmp(&c->cycle_key, &key, sizeof(CycleKey)) != 0) {
         rc = record_cycle(c, [&](hipStream_t st) { return enqueue_cycle(st, -1, maxit, false); });
         if (rc != IGS_OK) return rc;
@@ -917,7 +925,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
                                     hipMemcpyHostToDevice, s));
       HIP_OR_FAIL(c, hipGraphLaunch(c->cycle_exec, s));
     } else {
-      rc = enqueue_cycle(s, its_before, maxit_cycle, final_check);
+      rc = enqueue_cycle(s, its_before, maxit_cycle, check);
       if (rc != IGS_OK) return rc;
     }
     HIP_OR_FAIL(c, hipMemcpyAsync(c->h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -929,9 +937,9 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     if (prof) {
       // the iteration at which the cycle ended (every cycle ends by its tail)
       const int j_end = (h.end_iter == igs::kNotEnded) ? m : h.end_iter;
-      mark_cycle(c, j_end, m, final_check ? 0 : J, dn);
+      mark_cycle(c, j_end, m, check ? 0 : J, dn);
     }
-    if (cycles == 0 && !final_check) {
+    if (cycles == 0 && !check) {
       c->J_first = J;
       c->ldh_first = w.ldh;
       if (J > 0) {
@@ -961,7 +969,8 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
     }
     cycles += 1;
     relres = bnorm > 0 ? h.rho / bnorm : h.rho;
-    if (cycle_stagnated(rho_prev, h.rho)) stagnant += 1;
+    if (!skip_stagnation && cycle_stagnated(rho_prev, h.rho)) stagnant += 1;
+    skip_stagnation = false;
     rho_prev = h.rho;
     if (status == igs::kConvStart) {
       converged = true;
@@ -977,6 +986,13 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       ret = IGS_ENOCONV;
       break;
     }
+    if (probe) {
+      // the true residual is still above the tolerance: a full cycle from
+      // the same x
+      probe = false;
+      skip_stagnation = true;
+      continue;
+    }
     its += J;
     arn = bnorm > 0 ? h.gabs / bnorm : h.gabs;
     if (J == 0) {
@@ -984,6 +1000,7 @@ extern "C" int igs_solve_opts(igs_ctx* c, const double* b, double* x, int restar
       break;
     }
     if (its >= maxit || (o.max_cycles > 0 && cycles >= o.max_cycles)) final_check = true;
+    else if (status == igs::kConverged && h.gabs <= h.tol_abs) probe = true;
   }
   if (info) {
     info->iters = its;
@@ -1541,6 +1558,8 @@ struct Member {
   int cycles = 0;
   bool fresh = true;           // ||b|| not taken yet
   bool final_check = false;
+  bool probe = false;          // this cycle is a check cycle after an Arnoldi-converged one
+  bool skip_stagnation = false;
   bool done = false;
   bool converged = false;
   int rc = IGS_ENOCONV;
@@ -1627,14 +1646,15 @@ void batch_row(Batch& B, int k, const BatchParams& p) {
   I.b = M.b;
   I.x = M.x;
   I.its_before = M.its;
-  I.maxit = M.final_check ? M.its : M.maxit;   // a check cycle runs iteration 0 only
+  const bool check = M.final_check || M.probe;
+  I.maxit = check ? M.its : M.maxit;   // a check cycle runs iteration 0 only
   I.tol = p.tol;
   I.tau = p.tau;
   I.cycle_rtol = p.cycle_rtol;
   I.m = M.m;
   I.gs = p.gs;
   I.final_v = p.final_v;
-  I.run_lsq = M.final_check ? 0 : 1;
+  I.run_lsq = check ? 0 : 1;
 }
 
 // ||b|| and the finiteness of b and x0 for the members that just joined;
@@ -1690,7 +1710,7 @@ int batch_cycle(Batch& B, const BatchParams& p) {
     if (!M.c || M.done) continue;
     batch_row(B, k, p);
     all.act[all.count++] = k;
-    if (!M.final_check) jmax = std::max(jmax, M.m);
+    if (!M.final_check && !M.probe) jmax = std::max(jmax, M.m);
   }
   if (all.count == 0) return IGS_OK;
   BATCH_HIP(hipMemcpyAsync(B.d_tab, B.h_tab, sizeof(igs::Inst) * igs::kMaxBatch,
@@ -1706,7 +1726,7 @@ int batch_cycle(Batch& B, const BatchParams& p) {
     for (int q = 0; q < all.count; ++q) {
       const int k = all.act[q];
       const Member& M = B.mem[k];
-      const int mk = M.final_check ? 0 : M.m;   // a check cycle stops after iteration 0
+      const int mk = (M.final_check || M.probe) ? 0 : M.m;   // a check cycle stops after iteration 0
       if (j > mk) continue;
       up.act[up.count++] = k;
       if (j < M.m) {
@@ -1742,10 +1762,11 @@ int batch_cycle(Batch& B, const BatchParams& p) {
     M.status = h.status;
     M.breakdowns = h.breakdowns;
     M.fallbacks = h.fallbacks;
-    if (M.cycles == 0 && !M.final_check) M.J_first = J;
+    if (M.cycles == 0 && !M.final_check && !M.probe) M.J_first = J;
     M.cycles += 1;
     M.relres = M.bnorm > 0 ? h.rho / M.bnorm : h.rho;
-    if (cycle_stagnated(M.rho_prev, h.rho)) M.stagnant += 1;
+    if (!M.skip_stagnation && cycle_stagnated(M.rho_prev, h.rho)) M.stagnant += 1;
+    M.skip_stagnation = false;
     M.rho_prev = h.rho;
     if (M.status == igs::kConvStart) {
       M.converged = true;
@@ -1758,6 +1779,11 @@ int batch_cycle(Batch& B, const BatchParams& p) {
     } else if (M.final_check) {
       M.rc = IGS_ENOCONV;
       M.done = true;
+    } else if (M.probe) {
+      // as in a lone solve: the true residual is above the tolerance, a
+      // full cycle follows from the same x
+      M.probe = false;
+      M.skip_stagnation = true;
     } else {
       M.its += J;
       M.arn = M.bnorm > 0 ? h.gabs / M.bnorm : h.gabs;
@@ -1766,6 +1792,8 @@ int batch_cycle(Batch& B, const BatchParams& p) {
         M.done = true;
       } else if (M.its >= M.maxit || (p.max_cycles > 0 && M.cycles >= p.max_cycles)) {
         M.final_check = true;
+      } else if (M.status == igs::kConverged && h.gabs <= h.tol_abs) {
+        M.probe = true;
       }
     }
   }
