@@ -448,3 +448,21 @@ def test_stagnation_is_reported(torch):
     finally:
         for s in solvers:
             s.close()
+
+
+@pytest.mark.parametrize("side", [775, 1030])
+def test_one_cycle_x_with_ragged_vector_tiles(torch, side):
+    """x = x0 + V y at the end of a cycle where the x update runs 16-byte row
+    vectors with a ragged last tile (n = 600,625: four vectors of doubles per
+    thread, 2,048-row tiles; n = 1,060,900: eight, 4,096-row tiles): the
+    cycle's x and first Hessenberg columns against the oracle's cycle."""
+    a = W.convdiff2d(side, 20.0)
+    b = W.rhs_normal(a.n, 21)
+    print(f"one cycle, ragged vector tiles, n={a.n}", flush=True)
+    x, rc, info, H, _ = gpu(a, b, 30, 1e-12, 2, max_cycles=1)
+    ref = O.gmres(a, b, restart=30, tol=1e-12, variant="igs1r", max_cycles=1)
+    assert info["first_cycle_J"] == ref.first_cycle.J == 30
+    assert_H_close(H, ref.first_cycle.H)
+    dx = np.abs(x - ref.x).max() / np.abs(ref.x).max()
+    print(f"  max|x - x_oracle| / max|x_oracle| = {dx:.1e}", flush=True)
+    assert dx <= 1e-11
